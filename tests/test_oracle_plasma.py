@@ -1,0 +1,212 @@
+"""Pins of the oracle's grid map, fluid frame and thermal-synchrotron closure.
+
+Independent references: the MKS polar map itself (round trip), fields linear in (x1, x2)
+(bilinear interpolation is exact there), the normalisation identities of u and b, the
+closed-form gravitational redshift of a static emitter, scipy's K_2, the Planck integral
+(Stefan-Boltzmann) and its Rayleigh-Jeans / Wien limits, and the exact (ultra-relativistic)
+thermal synchrotron emissivity integrated numerically with scipy's K_{5/3}.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+import synthetic as S
+
+E_ESU, ME, C, H, KB = 4.80320471e-10, 9.1093837015e-28, 2.99792458e10, 6.62607015e-27, 1.380649e-16
+
+
+# ----------------------------------------------------------------------------- grid
+
+@pytest.mark.parametrize("h", [0.3, 0.7, 1.0])
+def test_mks_newton_round_trip(orc, h):
+    for x2 in np.linspace(0.0005, 0.9995, 41):
+        th = math.pi * x2 + 0.5 * (1 - h) * math.sin(2 * math.pi * x2)
+        got, it = orc.mks_x2(h, th)
+        assert abs(got - x2) < 1e-13 and it <= 50
+    if h == 1.0:
+        assert orc.mks_x2(1.0, 1.234)[0] == pytest.approx(1.234 / math.pi, abs=1e-15)
+
+
+def linear_grid(n1=16, n2=12, r_in=1.1, r_out=50.0, h=0.3):
+    lo, d1 = math.log(r_in), (math.log(r_out) - math.log(r_in)) / n1
+    x1c = lo + (np.arange(n1) + 0.5) * d1
+    x2c = (np.arange(n2) + 0.5) / n2
+    X2, X1 = np.meshgrid(x2c, x1c, indexing="ij")
+    cells = np.stack([3.0 + 2.0 * X1 - 5.0 * X2, 1.0 + X1 * 0.1, 7.0 - X2, 0.5 + X1 + X2], -1)[None]
+    g = S.Grid(cells=np.ascontiguousarray(cells), r_in=r_in, r_out=r_out, hslope=h, a_gen=0.0)
+    return g, (lambda x1, x2: np.array([3.0 + 2.0 * x1 - 5.0 * x2, 1.0 + 0.1 * x1, 7.0 - x2, 0.5 + x1 + x2]))
+
+
+def test_bilinear_exact_on_linear_fields_and_centres(orc):
+    g, f = linear_grid()
+    gh = orc.GridHandle(g)
+    lo, d1 = math.log(g.r_in), (math.log(g.r_out) - math.log(g.r_in)) / g.n1
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        # stay between the first and last centres, where no clamping applies
+        x1 = lo + d1 * rng.uniform(0.5, g.n1 - 0.5)
+        x2 = rng.uniform(0.5, g.n2 - 0.5) / g.n2
+        th = math.pi * x2 + 0.5 * (1 - g.hslope) * math.sin(2 * math.pi * x2)
+        v = orc.grid_sample(gh, math.exp(x1), th)
+        assert np.allclose(v, f(x1, x2), rtol=1e-12, atol=1e-12)
+    # cell centres reproduce the stored values
+    for (j, i) in [(0, 0), (5, 7), (11, 15)]:
+        x1 = lo + (i + 0.5) * d1
+        x2 = (j + 0.5) / g.n2
+        th = math.pi * x2 + 0.5 * (1 - g.hslope) * math.sin(2 * math.pi * x2)
+        assert np.allclose(orc.grid_sample(gh, math.exp(x1), th), g.cells[0, j, i], rtol=1e-12)
+    # outside the radial range there is no plasma
+    assert orc.grid_sample(gh, 1.05, 1.0) is None and orc.grid_sample(gh, 50.5, 1.0) is None
+
+
+def test_time_series_interpolation_and_fast_light_equivalence(orc):
+    base = S.make_grid(16, 16, a_gen=0.5, dtype=np.float64, n_snap=1)
+    # 4 identical snapshots, no modulation: slow light must equal fast light everywhere
+    stack = S.Grid(cells=np.repeat(base.cells, 4, axis=0), r_in=base.r_in, r_out=base.r_out,
+                   hslope=base.hslope, a_gen=0.5, t0=0.0, dt_snap=10.0)
+    gh = orc.GridHandle(stack)
+    for t in (-5.0, 3.0, 17.5, 29.0, 45.0):
+        a = orc.grid_sample(gh, 4.2, 1.3, 0.7, t, slow_light=1, t_frame=10.0)
+        b = orc.grid_sample(gh, 4.2, 1.3, 0.7, t, slow_light=0, t_frame=10.0)
+        assert np.allclose(a, b, rtol=2e-16, atol=0)
+    # snapshots scaled by (1 + s): the sampled density is linear in t between snapshots
+    cells = np.concatenate([base.cells * (1.0 + s) for s in range(4)], axis=0)
+    lin = S.Grid(cells=cells, r_in=base.r_in, r_out=base.r_out, hslope=base.hslope, a_gen=0.5,
+                 t0=0.0, dt_snap=10.0)
+    gl = orc.GridHandle(lin)
+    v0 = orc.grid_sample(gl, 4.2, 1.3, 0.0, 0.0, slow_light=1)
+    for t in (0.0, 4.0, 12.5, 30.0):
+        v = orc.grid_sample(gl, 4.2, 1.3, 0.0, t, slow_light=1)
+        assert np.allclose(v, v0 * (1.0 + t / 10.0), rtol=1e-12)
+    assert np.allclose(orc.grid_sample(gl, 4.2, 1.3, 0.0, 99.0, slow_light=1), v0 * 4.0, rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------- fluid frame
+
+@pytest.mark.parametrize("a,r,th,om", [(0.9375, 3.0, 1.2, 0.15), (0.0, 6.0, 1.0, 0.05),
+                                      (0.5, 1.9, 2.0, 0.9), (-0.7, 12.0, 0.4, 0.02)])
+def test_fluid_frame_normalisation(orc, a, r, th, om):
+    k = np.array([1.3, -0.4, 0.02, 0.07])
+    u, b, nr, cb, zamo = orc.fluid_frame(a, 1.0, [0, r, th, 0], k, om)
+    g = orc.ks_metric(a, 1.0, r, th)
+    assert u @ g @ u == pytest.approx(-1.0, abs=1e-13)
+    assert abs(b @ g @ u) < 1e-13
+    assert b @ g @ b == pytest.approx(1.0, abs=1e-13)
+    assert nr == pytest.approx(-(k @ g @ u), rel=1e-13)
+    assert -1.0 <= cb <= 1.0
+    if (a, r) == (0.5, 1.9):
+        assert zamo  # Omega = 0.9 is superluminal this close to the hole
+
+
+def test_static_emitter_redshift(orc):
+    """Static fluid: nu_r = 1 in flat space and 1/sqrt(1 - 2/r) around Schwarzschild."""
+    cam = S.Camera(spin=0.0, incl_deg=70.0, nx=2, ny=2)
+    y, _ = orc.camera_ray(cam, 3.0, -2.0, M=0.0)
+    _, _, nr, _, _ = orc.fluid_frame(0.0, 0.0, [0, 7.0, 1.1, 0.3], y[4:], 0.0)
+    assert nr == pytest.approx(1.0, abs=1e-13)
+    for r in (2.5, 4.0, 30.0):
+        # any null vector with k_t = -1 at that point
+        g = orc.ks_metric(0.0, 1.0, r, 1.0)
+        gi = np.linalg.inv(g)
+        kc = np.array([-1.0, 0.0, 0.3, 0.0])
+        qa, qb = gi[1, 1], 2 * gi[1, 0] * kc[0]
+        qc = gi[0, 0] + gi[2, 2] * kc[2] ** 2
+        kc[1] = (-qb + math.sqrt(qb * qb - 4 * qa * qc)) / (2 * qa)
+        k = gi @ kc
+        _, _, nr, _, _ = orc.fluid_frame(0.0, 1.0, [0, r, 1.0, 0], k, 0.0)
+        assert nr == pytest.approx(1.0 / math.sqrt(1.0 - 2.0 / r), rel=1e-12)
+
+
+# ----------------------------------------------------------------------------- closure
+
+@pytest.mark.parametrize("x", [0.01, 0.1, 0.5, 1.0, 3.0, 10.0])
+def test_bessel_k2_against_scipy(orc, x):
+    assert orc.bessel_k2(x) == pytest.approx(special.kn(2, x), rel=1e-13)
+
+
+def test_k2_paper_approximation_limit(orc):
+    """K2(1/Theta) / (2 Theta^2) -> 1 for hot electrons, which ties the paper's approximation
+    to the exact closure."""
+    for th, tol in [(10.0, 3e-3), (100.0, 3e-5), (1000.0, 3e-7)]:  # K2(x) = 2/x^2 - 1/2 + ...
+        assert orc.bessel_k2(1.0 / th) / (2 * th * th) == pytest.approx(1.0, rel=tol)
+    j_ex, _ = orc.closure(2e11, 1e5, 100.0, 3.0, 0.3, mode=orc.EXACT)
+    j_pa, _ = orc.closure(2e11, 1e5, 100.0, 3.0, 0.3, mode=orc.K2_PAPER)
+    assert j_pa / j_ex == pytest.approx(1.0, rel=1e-4)
+
+
+def test_planck_limits_and_stefan_boltzmann(orc):
+    from scipy import integrate
+    th = 0.5
+    T = th * ME * C * C / KB
+    nu_rj = 1e3
+    assert orc.planck(nu_rj, th) == pytest.approx(2 * nu_rj ** 2 * KB * T / C ** 2, rel=1e-9)
+    nu_w = 40 * KB * T / H
+    assert orc.planck(nu_w, th) == pytest.approx(2 * H * nu_w ** 3 / C ** 2 * math.exp(-H * nu_w / (KB * T)),
+                                                 rel=1e-15)
+    peak = KB * T / H
+    val, _ = integrate.quad(lambda lx: orc.planck(math.exp(lx) * peak, th) * math.exp(lx) * peak,
+                            math.log(1e-6), math.log(200), limit=400)
+    sigma_over_pi = 2 * math.pi ** 4 * KB ** 4 / (15 * C ** 2 * H ** 3)
+    assert val == pytest.approx(sigma_over_pi * T ** 4, rel=1e-8)
+
+
+def test_kirchhoff_and_rayleigh_jeans(orc):
+    for nu, ne, th, B, cb in [(230e9, 1e6, 10.0, 6.0, 0.3), (1e10, 3e4, 1.5, 0.7, -0.8), (1e15, 1e6, 5.0, 20.0, 0.1)]:
+        j, a = orc.closure(nu, ne, th, B, cb)
+        assert a * orc.planck(nu, th) == pytest.approx(j, rel=1e-13)
+        if nu < 1e12:
+            T = th * ME * C * C / KB
+            assert a == pytest.approx(j * C * C / (2 * nu * nu * KB * T), rel=1e-6)
+    assert orc.closure(230e9, 0.0, 10.0, 6.0, 0.3) == (0.0, 0.0)
+    assert orc.closure(230e9, 1e6, 10.0, 6.0, 1.0) == (0.0, 0.0)   # emission along the field
+    assert orc.closure(1.0, 1.0, 1.0, 1.0, 0.5, mode=orc.CONST, const_j=2.5, const_alpha=4.0) == (2.5, 4.0)
+
+
+def _exact_thermal_synchrotron():
+    """j_nu of a Maxwell-Juttner population from the ultra-relativistic single-electron
+    spectrum P_nu = sqrt(3) e^3 B sin(theta) / (m c^2) F(nu / nu_crit), nu_crit =
+    (3/2) gamma^2 nu_c sin(theta), F(x) = x int_x^inf K_{5/3}; j = n/(4 pi) int f(gamma) P dgamma."""
+    t = np.exp(np.linspace(math.log(1e-8), math.log(400.0), 200001))
+    f = special.kv(5.0 / 3.0, t) * t
+    seg = 0.5 * (f[1:] + f[:-1]) * np.diff(np.log(t))
+    tail = np.concatenate([np.cumsum(seg[::-1])[::-1], [0.0]])
+    lt, FT = np.log(t), t * tail
+
+    def j(nu, ne, th, B, theta):
+        nuc = E_ESU * B / (2 * math.pi * ME * C)
+        s = math.sin(theta)
+        lg = np.linspace(0.0, math.log(th * 80 + 50), 200001)
+        g = np.exp(lg)
+        f_mj = g * g * np.sqrt(np.maximum(0.0, 1 - 1 / g ** 2)) * np.exp(-g / th) / (th * special.kn(2, 1 / th))
+        x = nu / (1.5 * g * g * nuc * s)
+        Fx = np.interp(np.log(x), lt, FT, left=np.nan, right=0.0)
+        val = g * f_mj * math.sqrt(3) * E_ESU ** 3 * B * s / (ME * C * C) * Fx
+        return ne / (4 * math.pi) * np.trapezoid(val, lg)
+    return j
+
+
+def test_leung_fit_against_exact_thermal_synchrotron(orc):
+    """The fit of Sec. 4.2.2 against the exact emissivity in its hot, high-frequency regime.
+    Measured agreement is <= 2.2% (the paper quotes < 1% at 30 deg); the bound used is 3%,
+    which a dropped factor, exponent or term in the formula would exceed by far."""
+    jex = _exact_thermal_synchrotron()
+    worst = 0.0
+    for th in (3.0, 10.0, 30.0):
+        for deg in (30.0, 60.0):
+            for ratio in (1e2, 1e3, 1e4):
+                B = 10.0
+                nu = ratio * E_ESU * B / (2 * math.pi * ME * C)
+                jl, _ = orc.closure(nu, 1.0, th, B, math.cos(math.radians(deg)))
+                worst = max(worst, abs(jl / jex(nu, 1.0, th, B, math.radians(deg)) - 1))
+    assert worst < 0.03, worst
+
+
+def test_closure_scalings(orc):
+    """j is linear in n_e and depends on nu, B only through nu/nu_s times nu_s."""
+    j1, a1 = orc.closure(230e9, 1e5, 4.0, 5.0, 0.4)
+    j2, a2 = orc.closure(230e9, 3e5, 4.0, 5.0, 0.4)
+    assert j2 == pytest.approx(3 * j1, rel=1e-14) and a2 == pytest.approx(3 * a1, rel=1e-14)
+    j3, _ = orc.closure(460e9, 1e5, 4.0, 10.0, 0.4)   # same X, twice nu_s
+    assert j3 == pytest.approx(2 * j1, rel=1e-13)
