@@ -1,0 +1,175 @@
+/* raptor.h -- C ABI of the MI355X (gfx950) RAPTOR hot path.
+ *
+ * Method: Bronzwaer et al. 2018, "RAPTOR I: time-dependent radiative transfer in arbitrary
+ * spacetimes" (arXiv:1801.10452).  One ray per camera pixel is traced backward from the
+ * camera (Sec. 2.3, virtual camera) through the Kerr spacetime in Kerr-Schild coordinates
+ * (Sec. 2.4 and the appendix on coordinate transformations) with fourth-order Runge-Kutta
+ * (Sec. 2.2.1) and the adaptive step of Sec. 2.2, while the observed intensity is
+ * integrated along it with the backward scheme of Sec. 3.1 from thermal-synchrotron
+ * emission and Kirchhoff absorption (Sec. 4.2.2) sampled off an axisymmetric fluid grid
+ * in modified Kerr-Schild coordinates (appendix KS-MKS), optionally interpolated in time
+ * between snapshots (slow light, Sec. 5).
+ *
+ * Conventions for every entry point:
+ *  - Return RAPTOR_OK (0) or a negative raptor_status; no exception crosses the ABI.
+ *    raptor_last_error() then holds a message.  On RAPTOR_E_INVALID nothing is written.
+ *  - Calls are synchronous: outputs are complete when the call returns.
+ *  - The caller owns every buffer it passes; the library keeps no caller pointer after
+ *    returning.  Grids are copied to device memory owned by the context.
+ *  - Output buffers are host memory when opts->mem == RAPTOR_MEM_HOST and device memory
+ *    (of the context's device) when opts->mem == RAPTOR_MEM_DEVICE.  Frequencies, cameras
+ *    and option structs are always host memory.
+ *  - A context is used by one thread at a time; contexts are independent.
+ *  - Ray-level problems never fail a call: rays that hit the step limit, cross the pole or
+ *    become non-finite are counted in raptor_stats, and non-finite rays write 0.
+ *
+ * Units: geometric (G = c = 1, lengths and times in M) for the spacetime and the camera,
+ * CGS for the plasma, Hz for frequencies, erg s^-1 cm^-2 Hz^-1 sr^-1 for intensities and
+ * Jy for flux densities.
+ */
+#ifndef RAPTOR_H
+#define RAPTOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RAPTOR_OK = 0,
+    RAPTOR_E_INVALID = -1,      /* bad argument; nothing written */
+    RAPTOR_E_NOMEM = -2,        /* device allocation failed */
+    RAPTOR_E_DEVICE = -3,       /* HIP runtime error; outputs undefined */
+    RAPTOR_E_UNSUPPORTED = -4,  /* valid but not supported in this build */
+    RAPTOR_E_RANGE = -5         /* size limit exceeded */
+} raptor_status;
+
+enum { RAPTOR_F32 = 0, RAPTOR_F64 = 1 };
+enum { RAPTOR_MEM_HOST = 0, RAPTOR_MEM_DEVICE = 1 };
+/* Emission / absorption closure.  EXACT: the Leung et al. fit with the exact Bessel K2 and
+ * Kirchhoff absorption (Sec. 4.2.2).  K2_PAPER: same with the paper's K2 ~ 2 Theta_e^2.
+ * CONST: j = const_j, alpha = const_alpha wherever the grid has plasma (test closure).
+ * MLP: the learned surrogate (see raptor_mlp_*) inside its training box, EXACT outside. */
+enum { RAPTOR_CLOSURE_EXACT = 0, RAPTOR_CLOSURE_K2_PAPER = 1, RAPTOR_CLOSURE_CONST = 2,
+       RAPTOR_CLOSURE_MLP = 3 };
+/* Ray termination codes written by raptor_trace_spectrum_ex. */
+enum { RAPTOR_RAY_HORIZON = 1, RAPTOR_RAY_ESCAPED = 2, RAPTOR_RAY_MAXSTEP = 3,
+       RAPTOR_RAY_NUMERIC = 4 };
+
+enum { RAPTOR_MAX_NU = 32 };        /* frequencies per image */
+
+typedef struct raptor_ctx raptor_ctx;     /* opaque: device, stream, buffers, tuning cache */
+typedef struct raptor_grid raptor_grid;   /* opaque: device-resident fluid grid */
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is the stream all
+ * work is queued on; NULL makes the context create its own.  *out is set on success. */
+raptor_status raptor_create(int device, void* hip_stream, raptor_ctx** out);
+/* Release every device resource of the context (its grids included).  NULL is a no-op. */
+void raptor_destroy(raptor_ctx* ctx);
+/* Message of the last failed call on ctx (valid until the next call); "" if none.
+ * With ctx == NULL, the message of the last failed raptor_create on this thread. */
+const char* raptor_last_error(const raptor_ctx* ctx);
+
+/* Fluid grid: cells[n_snap][n2][n1][4] = {n_e [cm^-3], Theta_e, B [G], Omega [1/M]} at cell
+ * centres of a grid uniform in x1 = ln r over [ln r_in, ln r_out] and in x2 over [0, 1],
+ * theta(x2) = pi x2 + (1 - hslope)/2 sin(2 pi x2) (appendix KS-MKS).  Snapshot s is at
+ * coordinate time t0 + s dt_snap.  mod_amp, mod_phase describe an analytic azimuthal
+ * modulation of n_e, 1 + mod_amp sum_{m=1..4} cos(m (phi - Omega_K(r) t_s) + mod_phase[m-1])
+ * with Omega_K = 1/(r^1.5 + a_gen); mod_amp = 0 disables it.  Requires n1, n2 >= 2,
+ * n_snap >= 1, 0 < r_in < r_out, 0 < hslope <= 1, dt_snap > 0 when n_snap > 1, and dtype
+ * RAPTOR_F32 or RAPTOR_F64.  `cells` is host memory and is copied. */
+typedef struct {
+    int32_t n1, n2, n_snap, dtype;
+    double r_in, r_out, hslope, a_gen, t0, dt_snap;
+    double mod_amp, mod_phase[4];
+    const void* cells;
+} raptor_grid_desc;
+
+raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* desc, raptor_grid** out);
+void raptor_grid_release(raptor_ctx* ctx, raptor_grid* grid);
+
+/* Camera (Sec. 2.3): spin a (|a| < 1), inclination in degrees (0 < i < 180), camera radius
+ * r_cam and half field of view in M, nx x ny pixels.  Pixel (i, j) looks along impact
+ * parameters alpha = -F + (i + 1/2) 2F/nx, beta = -F + (j + 1/2) 2F/ny; images are stored
+ * row-major [j][i].  t_frame is the observation time: the ray leaves the camera at
+ * t = t_frame + r_cam, and fast light samples the snapshot nearest to t_frame. */
+typedef struct {
+    double spin, incl_deg, r_cam, fov_half;
+    int32_t nx, ny;
+    double t_frame;
+} raptor_camera;
+
+/* eps: step scale of the adaptive step (Sec. 2.2); r_stop_factor: rays stop at
+ * r < r_stop_factor * r_+; max_steps: step limit per ray; transfer_prec: RAPTOR_F64 or
+ * RAPTOR_F32 for the emission, absorption and intensity arithmetic (the geodesic is always
+ * FP64); closure: RAPTOR_CLOSURE_*; slow_light: 1 to interpolate snapshots along each ray;
+ * mem: RAPTOR_MEM_HOST or RAPTOR_MEM_DEVICE for output buffers; mass_msun and dist_pc set
+ * the length unit GM/c^2 and the flux distance; metric_mass is 1 (or 0 for flat space, which
+ * needs spin 0). */
+typedef struct {
+    double eps, r_stop_factor;
+    int32_t max_steps, transfer_prec, closure, slow_light, mem, reserved;
+    double mass_msun, dist_pc, const_j, const_alpha, metric_mass;
+} raptor_opts;
+
+/* Counters of the last trace call.  ray_steps counts accepted RK4 steps, samples the steps
+ * at which the plasma was sampled. */
+typedef struct {
+    uint64_t rays, ray_steps, samples, n_horizon, n_escaped, n_maxstep, n_pole, n_numeric,
+             n_mlp_fallback, n_zamo_fallback;
+    double kernel_ms;
+} raptor_stats;
+
+/* Fill *opts with the defaults: eps 0.05, r_stop_factor 1.01, max_steps 10000, FP64
+ * transfer, EXACT closure, fast light, host memory, 4.5e6 Msun at 8500 pc, metric_mass 1. */
+raptor_status raptor_default_opts(raptor_opts* opts);
+
+/* One image at one frequency.  image: double[ny][nx] or NULL; flux_jy: double or NULL;
+ * stats: may be NULL. */
+raptor_status raptor_trace_image(raptor_ctx* ctx, const raptor_camera* cam, const raptor_grid* grid,
+                                 const raptor_opts* opts, double nu_hz, double* image,
+                                 double* flux_jy, raptor_stats* stats);
+
+/* One image at n_nu frequencies on shared rays (the step is set by the geometry alone).
+ * nu_hz: host double[n_nu], 1 <= n_nu <= RAPTOR_MAX_NU, all > 0; images:
+ * double[n_nu][ny][nx] or NULL; flux_jy: double[n_nu] or NULL. */
+raptor_status raptor_trace_spectrum(raptor_ctx* ctx, const raptor_camera* cam, const raptor_grid* grid,
+                                    const raptor_opts* opts, const double* nu_hz, int32_t n_nu,
+                                    double* images, double* flux_jy, raptor_stats* stats);
+
+/* As raptor_trace_spectrum, and also writes the termination code and the number of
+ * accepted steps of every ray: ray_status, ray_steps: int32[ny][nx] or NULL (same memory
+ * kind as the images). */
+raptor_status raptor_trace_spectrum_ex(raptor_ctx* ctx, const raptor_camera* cam,
+                                       const raptor_grid* grid, const raptor_opts* opts,
+                                       const double* nu_hz, int32_t n_nu, double* images,
+                                       double* flux_jy, int32_t* ray_status, int32_t* ray_steps,
+                                       raptor_stats* stats);
+
+/* Many images of possibly different size, spin, inclination and grid in one persistent
+ * launch over a shared ray queue.  cams[n_cams]; grids[n_cams] (entries may repeat);
+ * nu_hz: host double[n_cams][n_nu]; images: the images of all cameras concatenated in
+ * camera order, each double[n_nu][ny][nx], or NULL; flux_jy: double[n_cams][n_nu] or NULL.
+ * Results equal the per-camera raptor_trace_spectrum calls. */
+raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                 const raptor_grid* const* grids, const raptor_opts* opts,
+                                 const double* nu_hz, int32_t n_nu, double* images, double* flux_jy,
+                                 raptor_stats* stats);
+
+/* Algorithmic work per unit, counted once on the host by running the kernel's scalar
+ * expressions through an operation-counting number type: FP64 add / sub / mul (a fused
+ * multiply-add counts 2) of one accepted RK4 step including the step rule (step_*), of the
+ * frequency-independent part of one plasma sample -- grid coordinates, one Newton iteration of
+ * the MKS map, bilinear interpolation, fluid frame, closure set-up (sample_*) -- and of the
+ * closure plus transfer update of one frequency at one sample (freq_*).  *_flops count
+ * arithmetic operations; *_special count divisions, square roots and transcendental calls,
+ * which are not included in *_flops.  Any pointer may be NULL. */
+raptor_status raptor_work_per_unit(double* step_flops, double* step_special, double* sample_flops,
+                                   double* sample_special, double* freq_flops, double* freq_special);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,56 @@
+// device_types.hpp -- plain structs shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+// Fluid grid resident in device memory, cells[n_snap][n2][n1] of float4 or double4
+// {n_e, Theta_e, B, Omega}.
+struct DevGrid {
+    const void* cells;
+    int n1, n2, n_snap, is_f64;
+    double lnr_in, inv_d1, r_in, r_out, hslope, a_gen, t0, dt_snap, inv_dt, mod_amp;
+    double mod_cos[4], mod_sin[4];   // cos / sin of the modulation phases
+};
+
+// One image of a launch.  Rays are numbered tile by tile (8 x 8 pixels per 64-ray tile);
+// the job owns the global tiles [tile_base, tile_base + tiles_x * tiles_y).
+struct DevJob {
+    double a, incl, sin_i, cos_i, r_cam, fov, dalpha, dbeta, r_stop, t_init;
+    long long tile_base;
+    long long out_base;    // offset of this job's first image in the intensity buffer (doubles)
+    long long pix_base;    // offset of this job's pixels in the per-ray info buffers
+    int nx, ny, tiles_x, n_nu;
+    int grid, nu_base, fast_snap, pad;
+};
+
+// ln K2(1/Theta) and its derivative in u = ln Theta at n uniform nodes u0 + i du.
+struct K2Table {
+    const double2* tab;
+    const float2* tabf;
+    int n, pad;
+    double u0, du, inv_du;
+};
+
+enum : int {
+    ST_RAYS = 0, ST_STEPS, ST_SAMPLES, ST_HORIZON, ST_ESCAPED, ST_MAXSTEP, ST_POLE, ST_NUMERIC,
+    ST_MLP_FALLBACK, ST_ZAMO, ST_COUNT
+};
+
+struct TraceParams {
+    const DevJob* jobs;
+    const DevGrid* grids;
+    const double* nu;          // frequencies, per job at nu_base
+    double* out;               // intensities [job image][n_nu][ny][nx]
+    int* ray_status;           // optional, per pixel at pix_base
+    int* ray_steps;            // optional
+    unsigned int* tile_counter;
+    unsigned long long* stats; // ST_COUNT counters
+    K2Table k2;
+    long long n_tiles;
+    int n_jobs, max_steps, closure, slow_light;
+    int refill_threshold, pad;
+    double eps, M, length_unit, const_j, const_alpha;
+};
+
+enum : int { CL_EXACT = 0, CL_K2_PAPER = 1, CL_CONST = 2, CL_MLP = 3 };
+enum : int { RAY_RUNNING = 0, RAY_HORIZON = 1, RAY_ESCAPED = 2, RAY_MAXSTEP = 3, RAY_NUMERIC = 4 };

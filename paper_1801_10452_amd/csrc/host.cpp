@@ -1,0 +1,638 @@
+// host.cpp -- the C ABI (include/raptor.h): context, validation, grid upload, job tables,
+// kernel launches, deterministic flux reduction, statistics and the work-per-unit count.
+#include "raptor.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "device_types.hpp"
+#include "ks_geodesic.hpp"
+#include "launch.hpp"
+#include "plasma.hpp"
+
+namespace rt {
+OpTally g_tally;
+}
+
+namespace {
+
+constexpr double kG = 6.67430e-8;
+constexpr double kMsun = 1.98847e33;
+constexpr double kPc = 3.085677581e18;
+constexpr double kC = 2.99792458e10;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string t_create_error;
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t cap = 0;
+    hipError_t reserve(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(n, 1);
+        hipError_t e = hipMalloc(&p, want * sizeof(T));
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+}  // namespace
+
+struct raptor_grid {
+    DevGrid d{};
+    void* cells = nullptr;
+    raptor_ctx* owner = nullptr;
+};
+
+struct LaunchPlan {
+    int threads = 256;
+    int blocks = 0;
+    int refill = 1;
+};
+
+struct raptor_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 0;
+    std::string err;
+    DevBuf<DevJob> jobs;
+    DevBuf<DevGrid> grids;
+    DevBuf<double> nu, out, pixsr, flux;
+    DevBuf<int> status, steps;
+    DevBuf<unsigned int> counter;
+    DevBuf<unsigned long long> stats;
+    DevBuf<double2> k2;
+    DevBuf<float2> k2f;
+    K2Table k2t{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<raptor_grid*> live;
+    std::map<int, LaunchPlan> plans;   // key: max_nu * 2 + fp32
+};
+
+namespace {
+
+raptor_status fail(raptor_ctx* ctx, raptor_status s, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+raptor_status dev_fail(raptor_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? RAPTOR_E_NOMEM : RAPTOR_E_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define RAPTOR_CK(call, what)                         \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return dev_fail(ctx, e_, what); \
+    } while (0)
+
+// Table of ln K2(1/Theta) and its derivative in u = ln Theta (d/du ln K2 = x K1/K2 + 2,
+// x = 1/Theta), from the C++17 library Bessel functions; Theta in [1e-2, 1e4].
+raptor_status build_k2_table(raptor_ctx* ctx)
+{
+    const int n = 4096;
+    const double u0 = std::log(1e-2), u1 = std::log(1e4);
+    const double du = (u1 - u0) / (n - 1);
+    std::vector<double2> h(n);
+    std::vector<float2> hf(n);
+    for (int i = 0; i < n; ++i) {
+        const double u = u0 + i * du;
+        const double x = std::exp(-u);
+        const double k1 = std::cyl_bessel_k(1.0, x), k2 = std::cyl_bessel_k(2.0, x);
+        h[i].x = std::log(k2);
+        h[i].y = x * k1 / k2 + 2.0;
+        hf[i].x = (float)h[i].x;
+        hf[i].y = (float)h[i].y;
+    }
+    RAPTOR_CK(ctx->k2.reserve(n), "allocating the K2 table");
+    RAPTOR_CK(ctx->k2f.reserve(n), "allocating the K2 table");
+    RAPTOR_CK(hipMemcpy(ctx->k2.p, h.data(), n * sizeof(double2), hipMemcpyHostToDevice), "uploading the K2 table");
+    RAPTOR_CK(hipMemcpy(ctx->k2f.p, hf.data(), n * sizeof(float2), hipMemcpyHostToDevice), "uploading the K2 table");
+    ctx->k2t.tab = ctx->k2.p;
+    ctx->k2t.tabf = ctx->k2f.p;
+    ctx->k2t.n = n;
+    ctx->k2t.u0 = u0;
+    ctx->k2t.du = du;
+    ctx->k2t.inv_du = 1.0 / du;
+    return RAPTOR_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+raptor_status check_opts(raptor_ctx* ctx, const raptor_opts* o)
+{
+    if (!o) return fail(ctx, RAPTOR_E_INVALID, "opts is NULL");
+    if (!finite_pos(o->eps) || o->eps > 1.0) return fail(ctx, RAPTOR_E_INVALID, "eps must be in (0, 1]");
+    if (!(std::isfinite(o->r_stop_factor) && o->r_stop_factor >= 1.0))
+        return fail(ctx, RAPTOR_E_INVALID, "r_stop_factor must be >= 1");
+    if (o->max_steps < 1) return fail(ctx, RAPTOR_E_INVALID, "max_steps must be >= 1");
+    if (o->transfer_prec != RAPTOR_F32 && o->transfer_prec != RAPTOR_F64)
+        return fail(ctx, RAPTOR_E_INVALID, "transfer_prec must be RAPTOR_F32 or RAPTOR_F64");
+    if (o->closure < RAPTOR_CLOSURE_EXACT || o->closure > RAPTOR_CLOSURE_MLP)
+        return fail(ctx, RAPTOR_E_INVALID, "unknown closure");
+    if (o->closure == RAPTOR_CLOSURE_MLP) return fail(ctx, RAPTOR_E_UNSUPPORTED, "MLP closure has no weights loaded");
+    if (o->slow_light != 0 && o->slow_light != 1) return fail(ctx, RAPTOR_E_INVALID, "slow_light must be 0 or 1");
+    if (o->mem != RAPTOR_MEM_HOST && o->mem != RAPTOR_MEM_DEVICE) return fail(ctx, RAPTOR_E_INVALID, "unknown mem");
+    if (!finite_pos(o->mass_msun) || !finite_pos(o->dist_pc))
+        return fail(ctx, RAPTOR_E_INVALID, "mass_msun and dist_pc must be positive");
+    if (o->metric_mass != 0.0 && o->metric_mass != 1.0) return fail(ctx, RAPTOR_E_INVALID, "metric_mass must be 0 or 1");
+    if (o->closure == RAPTOR_CLOSURE_CONST && !(std::isfinite(o->const_j) && std::isfinite(o->const_alpha) &&
+                                                o->const_j >= 0.0 && o->const_alpha >= 0.0))
+        return fail(ctx, RAPTOR_E_INVALID, "const_j and const_alpha must be finite and >= 0");
+    return RAPTOR_OK;
+}
+
+raptor_status check_camera(raptor_ctx* ctx, const raptor_camera* c, const raptor_grid* g, const raptor_opts* o, int k)
+{
+    char buf[160];
+    if (!c) return fail(ctx, RAPTOR_E_INVALID, "camera is NULL");
+    if (!g) return fail(ctx, RAPTOR_E_INVALID, "grid is NULL");
+    if (g->owner != ctx) return fail(ctx, RAPTOR_E_INVALID, "grid belongs to another context");
+    const double M = o->metric_mass;
+    if (!(std::isfinite(c->spin) && std::fabs(c->spin) < 1.0) || (M == 0.0 && c->spin != 0.0)) {
+        std::snprintf(buf, sizeof buf, "camera %d: spin must satisfy |a| < 1 (and a = 0 in flat space)", k);
+        return fail(ctx, RAPTOR_E_INVALID, buf);
+    }
+    if (!(c->incl_deg > 0.0 && c->incl_deg < 180.0)) {
+        std::snprintf(buf, sizeof buf, "camera %d: inclination must be in (0, 180) degrees", k);
+        return fail(ctx, RAPTOR_E_INVALID, buf);
+    }
+    const double rh = M + std::sqrt(std::max(M * M - c->spin * c->spin, 0.0));
+    if (!(std::isfinite(c->r_cam) && c->r_cam > g->d.r_out && c->r_cam > o->r_stop_factor * rh)) {
+        std::snprintf(buf, sizeof buf, "camera %d: r_cam must exceed the grid's r_out and the stop radius", k);
+        return fail(ctx, RAPTOR_E_INVALID, buf);
+    }
+    if (!finite_pos(c->fov_half)) return fail(ctx, RAPTOR_E_INVALID, "fov_half must be positive");
+    if (c->nx < 1 || c->ny < 1 || c->nx > 65536 || c->ny > 65536) {
+        std::snprintf(buf, sizeof buf, "camera %d: nx, ny must be in [1, 65536]", k);
+        return fail(ctx, RAPTOR_E_INVALID, buf);
+    }
+    if (!std::isfinite(c->t_frame)) return fail(ctx, RAPTOR_E_INVALID, "t_frame must be finite");
+    return RAPTOR_OK;
+}
+
+struct JobIn {
+    const raptor_camera* cam;
+    const raptor_grid* grid;
+    const double* nu;
+};
+
+raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out)
+{
+    const int key = max_nu * 2 + (fp32 ? 1 : 0);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) {
+        *out = it->second;
+        return RAPTOR_OK;
+    }
+    LaunchPlan pl;
+    int per_cu = 0;
+    RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel_symbol(max_nu, fp32), pl.threads, 0),
+              "querying occupancy");
+    pl.blocks = ctx->cu_count * std::max(per_cu, 1);
+    ctx->plans[key] = pl;
+    *out = pl;
+    return RAPTOR_OK;
+}
+
+raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, const raptor_opts* o,
+                       double* images, double* flux_jy, int32_t* ray_status, int32_t* ray_steps, raptor_stats* st)
+{
+    const bool dev = o->mem == RAPTOR_MEM_DEVICE;
+    const int nj = (int)in.size();
+    // ---- job table
+    std::vector<DevJob> jobs(nj);
+    std::vector<const raptor_grid*> gl;
+    std::vector<double> nus, pixsr(nj);
+    long long tiles = 0, outn = 0, pixn = 0;
+    const double M = o->metric_mass;
+    const double Lu = kG * o->mass_msun * kMsun / (kC * kC);
+    const double D = o->dist_pc * kPc;
+    for (int k = 0; k < nj; ++k) {
+        const raptor_camera& c = *in[k].cam;
+        DevJob& J = jobs[k];
+        std::memset(&J, 0, sizeof J);
+        J.a = c.spin;
+        J.incl = c.incl_deg * kPi / 180.0;
+        J.sin_i = std::sqrt(1.0 - std::cos(J.incl) * std::cos(J.incl));
+        J.cos_i = std::cos(J.incl);
+        J.r_cam = c.r_cam;
+        J.fov = c.fov_half;
+        J.dalpha = 2.0 * c.fov_half / c.nx;
+        J.dbeta = 2.0 * c.fov_half / c.ny;
+        J.r_stop = o->r_stop_factor * (M + std::sqrt(std::max(M * M - c.spin * c.spin, 0.0)));
+        J.t_init = c.t_frame + c.r_cam;
+        J.nx = c.nx;
+        J.ny = c.ny;
+        J.tiles_x = (c.nx + 7) / 8;
+        J.n_nu = n_nu;
+        J.tile_base = tiles;
+        J.out_base = outn;
+        J.pix_base = pixn;
+        tiles += (long long)J.tiles_x * ((c.ny + 7) / 8);
+        outn += (long long)n_nu * c.nx * c.ny;
+        pixn += (long long)c.nx * c.ny;
+        auto gi = std::find(gl.begin(), gl.end(), in[k].grid);
+        J.grid = (int)(gi - gl.begin());
+        if (gi == gl.end()) gl.push_back(in[k].grid);
+        const DevGrid& G = in[k].grid->d;
+        int fs = 0;
+        if (G.n_snap > 1) {
+            fs = (int)std::floor((c.t_frame - G.t0) / G.dt_snap + 0.5);
+            fs = std::min(std::max(fs, 0), G.n_snap - 1);
+        }
+        J.fast_snap = fs;
+        J.nu_base = (int)nus.size();
+        for (int f = 0; f < n_nu; ++f) nus.push_back(in[k].nu[f]);
+        pixsr[k] = J.dalpha * J.dbeta * Lu * Lu / (D * D);
+    }
+    if (tiles >= (1ll << 31) - 1) return fail(ctx, RAPTOR_E_RANGE, "too many pixels in one call");
+    std::vector<DevGrid> grids(gl.size());
+    for (size_t i = 0; i < gl.size(); ++i) grids[i] = gl[i]->d;
+
+    // ---- device buffers
+    RAPTOR_CK(ctx->jobs.reserve(nj), "allocating the job table");
+    RAPTOR_CK(ctx->grids.reserve(grids.size()), "allocating the grid table");
+    RAPTOR_CK(ctx->nu.reserve(nus.size()), "allocating frequencies");
+    RAPTOR_CK(ctx->pixsr.reserve(nj), "allocating solid angles");
+    RAPTOR_CK(ctx->flux.reserve((size_t)nj * n_nu), "allocating fluxes");
+    double* out = nullptr;
+    if (dev && images) {
+        out = images;
+    } else {
+        RAPTOR_CK(ctx->out.reserve(outn), "allocating intensities");
+        out = ctx->out.p;
+    }
+    int* rs = nullptr;
+    int* rn = nullptr;
+    if (ray_status || ray_steps) {
+        if (dev) {
+            rs = ray_status;
+            rn = ray_steps;
+        } else {
+            RAPTOR_CK(ctx->status.reserve(pixn), "allocating ray info");
+            RAPTOR_CK(ctx->steps.reserve(pixn), "allocating ray info");
+            rs = ray_status ? ctx->status.p : nullptr;
+            rn = ray_steps ? ctx->steps.p : nullptr;
+        }
+    }
+    hipStream_t s = ctx->stream;
+    RAPTOR_CK(hipMemcpyAsync(ctx->jobs.p, jobs.data(), nj * sizeof(DevJob), hipMemcpyHostToDevice, s), "uploading jobs");
+    RAPTOR_CK(hipMemcpyAsync(ctx->grids.p, grids.data(), grids.size() * sizeof(DevGrid), hipMemcpyHostToDevice, s),
+              "uploading the grid table");
+    RAPTOR_CK(hipMemcpyAsync(ctx->nu.p, nus.data(), nus.size() * sizeof(double), hipMemcpyHostToDevice, s),
+              "uploading frequencies");
+    RAPTOR_CK(hipMemcpyAsync(ctx->pixsr.p, pixsr.data(), nj * sizeof(double), hipMemcpyHostToDevice, s),
+              "uploading solid angles");
+
+    TraceParams p{};
+    p.jobs = ctx->jobs.p;
+    p.grids = ctx->grids.p;
+    p.nu = ctx->nu.p;
+    p.out = out;
+    p.ray_status = rs;
+    p.ray_steps = rn;
+    p.tile_counter = ctx->counter.p;
+    p.stats = ctx->stats.p;
+    p.k2 = ctx->k2t;
+    p.n_tiles = tiles;
+    p.n_jobs = nj;
+    p.max_steps = o->max_steps;
+    p.closure = o->closure;
+    p.slow_light = o->slow_light;
+    p.eps = o->eps;
+    p.M = M;
+    p.length_unit = Lu;
+    p.const_j = o->const_j;
+    p.const_alpha = o->const_alpha;
+    const bool fp32 = o->transfer_prec == RAPTOR_F32;
+    LaunchPlan plan;
+    raptor_status ps = plan_for(ctx, n_nu, fp32, &plan);
+    if (ps != RAPTOR_OK) return ps;
+    p.refill_threshold = plan.refill;
+
+    RAPTOR_CK(launch_reset(ctx->counter.p, ctx->stats.p, s), "launching reset");
+    RAPTOR_CK(hipEventRecord(ctx->ev0, s), "recording an event");
+    RAPTOR_CK(launch_trace(p, n_nu, fp32, plan.blocks, plan.threads, s), "launching the trace kernel");
+    RAPTOR_CK(hipEventRecord(ctx->ev1, s), "recording an event");
+    RAPTOR_CK(launch_flux(ctx->jobs.p, nj, out, ctx->pixsr.p, ctx->flux.p, n_nu, s), "launching the flux reduction");
+
+    const hipMemcpyKind d2x = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (images && out != images)
+        RAPTOR_CK(hipMemcpyAsync(images, out, outn * sizeof(double), d2x, s), "copying images");
+    if (flux_jy)
+        RAPTOR_CK(hipMemcpyAsync(flux_jy, ctx->flux.p, (size_t)nj * n_nu * sizeof(double), d2x, s), "copying fluxes");
+    if (ray_status && rs != ray_status)
+        RAPTOR_CK(hipMemcpyAsync(ray_status, rs, pixn * sizeof(int), d2x, s), "copying ray status");
+    if (ray_steps && rn != ray_steps)
+        RAPTOR_CK(hipMemcpyAsync(ray_steps, rn, pixn * sizeof(int), d2x, s), "copying ray steps");
+    unsigned long long hs[ST_COUNT];
+    RAPTOR_CK(hipMemcpyAsync(hs, ctx->stats.p, sizeof hs, hipMemcpyDeviceToHost, s), "copying statistics");
+    RAPTOR_CK(hipStreamSynchronize(s), "running the trace");
+    if (st) {
+        st->rays = hs[ST_RAYS];
+        st->ray_steps = hs[ST_STEPS];
+        st->samples = hs[ST_SAMPLES];
+        st->n_horizon = hs[ST_HORIZON];
+        st->n_escaped = hs[ST_ESCAPED];
+        st->n_maxstep = hs[ST_MAXSTEP];
+        st->n_pole = hs[ST_POLE];
+        st->n_numeric = hs[ST_NUMERIC];
+        st->n_mlp_fallback = hs[ST_MLP_FALLBACK];
+        st->n_zamo_fallback = hs[ST_ZAMO];
+        float ms = 0.0f;
+        RAPTOR_CK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "reading the kernel time");
+        st->kernel_ms = ms;
+    }
+    return RAPTOR_OK;
+}
+
+raptor_status check_nu(raptor_ctx* ctx, const double* nu, int n_nu)
+{
+    if (!nu) return fail(ctx, RAPTOR_E_INVALID, "nu_hz is NULL");
+    if (n_nu < 1 || n_nu > RAPTOR_MAX_NU) return fail(ctx, RAPTOR_E_INVALID, "n_nu must be in [1, RAPTOR_MAX_NU]");
+    for (int f = 0; f < n_nu; ++f)
+        if (!finite_pos(nu[f])) return fail(ctx, RAPTOR_E_INVALID, "frequencies must be finite and > 0");
+    return RAPTOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+raptor_status raptor_create(int device, void* hip_stream, raptor_ctx** out)
+{
+    t_create_error.clear();
+    if (!out) {
+        t_create_error = "out is NULL";
+        return RAPTOR_E_INVALID;
+    }
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        t_create_error = "no HIP device";
+        return RAPTOR_E_DEVICE;
+    }
+    if (device < 0 || device >= n) {
+        t_create_error = "device index out of range";
+        return RAPTOR_E_INVALID;
+    }
+    raptor_ctx* ctx = new raptor_ctx();
+    ctx->device = device;
+    auto bail = [&](raptor_status s) {
+        t_create_error = ctx->err;
+        raptor_destroy(ctx);
+        return s;
+    };
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return bail(dev_fail(ctx, e, "selecting the device"));
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(dev_fail(ctx, e, "creating a stream"));
+        ctx->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return bail(dev_fail(ctx, e, "reading device properties"));
+    ctx->cu_count = prop.multiProcessorCount;
+    if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess || (e = hipEventCreate(&ctx->ev1)) != hipSuccess)
+        return bail(dev_fail(ctx, e, "creating events"));
+    if ((e = ctx->counter.reserve(1)) != hipSuccess || (e = ctx->stats.reserve(ST_COUNT)) != hipSuccess)
+        return bail(dev_fail(ctx, e, "allocating counters"));
+    raptor_status s = build_k2_table(ctx);
+    if (s != RAPTOR_OK) return bail(s);
+    *out = ctx;
+    return RAPTOR_OK;
+}
+
+void raptor_destroy(raptor_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (raptor_grid* g : ctx->live) {
+        if (g->cells) (void)hipFree(g->cells);
+        delete g;
+    }
+    ctx->jobs.release();
+    ctx->grids.release();
+    ctx->nu.release();
+    ctx->out.release();
+    ctx->pixsr.release();
+    ctx->flux.release();
+    ctx->status.release();
+    ctx->steps.release();
+    ctx->counter.release();
+    ctx->stats.release();
+    ctx->k2.release();
+    ctx->k2f.release();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* raptor_last_error(const raptor_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : t_create_error.c_str();
+}
+
+raptor_status raptor_default_opts(raptor_opts* o)
+{
+    if (!o) return RAPTOR_E_INVALID;
+    std::memset(o, 0, sizeof *o);
+    o->eps = 0.05;
+    o->r_stop_factor = 1.01;
+    o->max_steps = 10000;
+    o->transfer_prec = RAPTOR_F64;
+    o->closure = RAPTOR_CLOSURE_EXACT;
+    o->slow_light = 0;
+    o->mem = RAPTOR_MEM_HOST;
+    o->mass_msun = 4.5e6;
+    o->dist_pc = 8500.0;
+    o->metric_mass = 1.0;
+    return RAPTOR_OK;
+}
+
+raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, raptor_grid** out)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    if (!d || !out || !d->cells) return fail(ctx, RAPTOR_E_INVALID, "desc, desc->cells and out must be non-NULL");
+    if (d->n1 < 2 || d->n2 < 2 || d->n_snap < 1) return fail(ctx, RAPTOR_E_INVALID, "need n1, n2 >= 2 and n_snap >= 1");
+    if (d->dtype != RAPTOR_F32 && d->dtype != RAPTOR_F64) return fail(ctx, RAPTOR_E_INVALID, "unknown grid dtype");
+    if (!(finite_pos(d->r_in) && std::isfinite(d->r_out) && d->r_out > d->r_in))
+        return fail(ctx, RAPTOR_E_INVALID, "need 0 < r_in < r_out");
+    if (!(d->hslope > 0.0 && d->hslope <= 1.0)) return fail(ctx, RAPTOR_E_INVALID, "hslope must be in (0, 1]");
+    if (d->n_snap > 1 && !finite_pos(d->dt_snap)) return fail(ctx, RAPTOR_E_INVALID, "dt_snap must be > 0");
+    if (!std::isfinite(d->t0) || !std::isfinite(d->mod_amp) || !std::isfinite(d->a_gen))
+        return fail(ctx, RAPTOR_E_INVALID, "t0, mod_amp and a_gen must be finite");
+    *out = nullptr;
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    const size_t cell = d->dtype == RAPTOR_F64 ? 4 * sizeof(double) : 4 * sizeof(float);
+    const size_t bytes = (size_t)d->n_snap * d->n2 * d->n1 * cell;
+    raptor_grid* g = new raptor_grid();
+    hipError_t e = hipMalloc(&g->cells, bytes);
+    if (e != hipSuccess) {
+        delete g;
+        return dev_fail(ctx, e, "allocating the grid");
+    }
+    e = hipMemcpy(g->cells, d->cells, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(g->cells);
+        delete g;
+        return dev_fail(ctx, e, "uploading the grid");
+    }
+    DevGrid& G = g->d;
+    G.cells = g->cells;
+    G.n1 = d->n1;
+    G.n2 = d->n2;
+    G.n_snap = d->n_snap;
+    G.is_f64 = d->dtype == RAPTOR_F64;
+    G.lnr_in = std::log(d->r_in);
+    G.inv_d1 = d->n1 / (std::log(d->r_out) - std::log(d->r_in));
+    G.r_in = d->r_in;
+    G.r_out = d->r_out;
+    G.hslope = d->hslope;
+    G.a_gen = d->a_gen;
+    G.t0 = d->t0;
+    G.dt_snap = d->n_snap > 1 ? d->dt_snap : 1.0;
+    G.inv_dt = 1.0 / G.dt_snap;
+    G.mod_amp = d->mod_amp;
+    for (int m = 0; m < 4; ++m) {
+        G.mod_cos[m] = std::cos(d->mod_phase[m]);
+        G.mod_sin[m] = std::sin(d->mod_phase[m]);
+    }
+    g->owner = ctx;
+    ctx->live.push_back(g);
+    *out = g;
+    return RAPTOR_OK;
+}
+
+void raptor_grid_release(raptor_ctx* ctx, raptor_grid* g)
+{
+    if (!ctx || !g) return;
+    auto it = std::find(ctx->live.begin(), ctx->live.end(), g);
+    if (it == ctx->live.end()) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (g->cells) (void)hipFree(g->cells);
+    ctx->live.erase(it);
+    delete g;
+}
+
+raptor_status raptor_trace_spectrum_ex(raptor_ctx* ctx, const raptor_camera* cam, const raptor_grid* grid,
+                                       const raptor_opts* opts, const double* nu_hz, int32_t n_nu, double* images,
+                                       double* flux_jy, int32_t* ray_status, int32_t* ray_steps, raptor_stats* stats)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    raptor_status s;
+    if ((s = check_opts(ctx, opts)) != RAPTOR_OK) return s;
+    if ((s = check_nu(ctx, nu_hz, n_nu)) != RAPTOR_OK) return s;
+    if ((s = check_camera(ctx, cam, grid, opts, 0)) != RAPTOR_OK) return s;
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    std::vector<JobIn> in{{cam, grid, nu_hz}};
+    return run_jobs(ctx, in, n_nu, opts, images, flux_jy, ray_status, ray_steps, stats);
+}
+
+raptor_status raptor_trace_spectrum(raptor_ctx* ctx, const raptor_camera* cam, const raptor_grid* grid,
+                                    const raptor_opts* opts, const double* nu_hz, int32_t n_nu, double* images,
+                                    double* flux_jy, raptor_stats* stats)
+{
+    return raptor_trace_spectrum_ex(ctx, cam, grid, opts, nu_hz, n_nu, images, flux_jy, nullptr, nullptr, stats);
+}
+
+raptor_status raptor_trace_image(raptor_ctx* ctx, const raptor_camera* cam, const raptor_grid* grid,
+                                 const raptor_opts* opts, double nu_hz, double* image, double* flux_jy,
+                                 raptor_stats* stats)
+{
+    return raptor_trace_spectrum_ex(ctx, cam, grid, opts, &nu_hz, 1, image, flux_jy, nullptr, nullptr, stats);
+}
+
+raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                 const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz,
+                                 int32_t n_nu, double* images, double* flux_jy, raptor_stats* stats)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    raptor_status s;
+    if (!cams || !grids || n_cams < 1) return fail(ctx, RAPTOR_E_INVALID, "need n_cams >= 1 cameras and grids");
+    if ((s = check_opts(ctx, opts)) != RAPTOR_OK) return s;
+    if (!nu_hz) return fail(ctx, RAPTOR_E_INVALID, "nu_hz is NULL");
+    std::vector<JobIn> in(n_cams);
+    for (int k = 0; k < n_cams; ++k) {
+        if ((s = check_nu(ctx, nu_hz + (size_t)k * n_nu, n_nu)) != RAPTOR_OK) return s;
+        if ((s = check_camera(ctx, &cams[k], grids[k], opts, k)) != RAPTOR_OK) return s;
+        in[k] = {&cams[k], grids[k], nu_hz + (size_t)k * n_nu};
+    }
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    return run_jobs(ctx, in, n_nu, opts, images, flux_jy, nullptr, nullptr, stats);
+}
+
+raptor_status raptor_work_per_unit(double* step_flops, double* step_special, double* sample_flops,
+                                   double* sample_special, double* freq_flops, double* freq_special)
+{
+    using C = rt::OpCounted;
+    // one accepted step at a representative state (the count does not depend on the values)
+    C y[8] = {C(0.0), C(9.0), C(1.1), C(0.3), C(1.05), C(-0.9), C(0.02), C(0.01)};
+    rt::g_tally = rt::OpTally{};
+    const rk::Spin<C> sp = rk::make_spin(C(0.9375), C(1.0));
+    const C dl = -rk::step_size(C(0.05), y);
+    rk::rk4_step(sp, y, dl);
+    if (step_flops) *step_flops = rt::g_tally.flops;
+    if (step_special) *step_special = rt::g_tally.special;
+
+    // one sample, frequency-independent part: grid coordinates (7), one Newton iteration of
+    // the MKS map, bilinear interpolation, fluid frame, path length (2), 1/nu_r^3 (2), sin
+    // theta_B (2), K2 lookup (Hermite, 20)
+    const double root = pl::mks_x2(0.3, rt::val(y[2]), rt::val(y[2]) / kPi);
+    rt::g_tally = rt::OpTally{};
+    (void)rt::log_(y[1]);
+    rt::g_tally.flops += 7;
+    (void)pl::mks_x2(C(0.3), y[2], C(root));   // starts at the root: exactly one iteration
+    C a[4] = {1, 2, 3, 4}, b[4] = {1, 2, 3, 4}, c[4] = {1, 2, 3, 4}, d[4] = {1, 2, 3, 4}, o4[4];
+    pl::bilerp4(a, b, c, d, C(0.3), C(0.6), o4);
+    C nr, cb;
+    (void)pl::fluid_frame(C(0.9375), C(0.9375 * 0.9375), C(1.0), y, C(0.05), &nr, &cb);
+    rt::g_tally.flops += 2 + 2 + 2 + 20;
+    rt::g_tally.special += 1 + 1 + 2;   // 1/nu_r^3, sqrt, log + exp of the K2 lookup
+    if (sample_flops) *sample_flops = rt::g_tally.flops;
+    if (sample_special) *sample_special = rt::g_tally.special;
+
+    // closure and transfer update of one frequency
+    rt::g_tally = rt::OpTally{};
+    C nu = C(230e9) * nr;
+    C j, al, S, I = C(0.0), tau = C(0.0);
+    pl::closure_exact(nu, C(1e5), C(3.0), C(5.0), C(0.5), C(0.01), &j, &al, &S);
+    pl::transfer_update(j, al, S, C(1e10), C(0.8), I, tau);
+    if (freq_flops) *freq_flops = rt::g_tally.flops;
+    if (freq_special) *freq_special = rt::g_tally.special;
+    return RAPTOR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// plasma.hpp -- fluid sampling, fluid frame, thermal-synchrotron closure, transfer update.
+#pragma once
+#include "device_types.hpp"
+#include "rt_math.hpp"
+
+namespace pl {
+
+// CGS constants (CODATA 2018).
+constexpr double C_LIGHT = 2.99792458e10;
+constexpr double Q_E = 4.80320471e-10;
+constexpr double ME_CGS = 9.1093837015e-28;
+constexpr double H_PLANCK = 6.62607015e-27;
+constexpr double PI_D = 3.14159265358979323846;
+constexpr double NUC_PER_GAUSS = Q_E / (2.0 * PI_D * ME_CGS * C_LIGHT);      // e/(2 pi m_e c)
+constexpr double J_PREF = 1.4142135623730951 * PI_D * Q_E * Q_E / (3.0 * C_LIGHT);  // sqrt2 pi e^2/(3c)
+constexpr double TWO_11_12 = 1.8877486253633868;                          // 2^(11/12)
+constexpr double PLANCK_PREF = 2.0 * H_PLANCK / (C_LIGHT * C_LIGHT);      // 2h/c^2
+constexpr double H_OVER_MEC2 = H_PLANCK / (ME_CGS * C_LIGHT * C_LIGHT);      // h/(m_e c^2)
+
+// theta -> x2 of the MKS polar map theta = pi x2 + (1-h)/2 sin(2 pi x2) (appendix KS-MKS) by
+// Newton-Raphson from x0, with the paper's reset to 0.05 when an iterate leaves [0, 1] or the
+// derivative vanishes, until two iterates differ by less than 1e-14 (at most 50 iterations).
+template <class T>
+__host__ __device__ inline T mks_x2(T h, T th, T x0)
+{
+    using namespace rt;
+    T x = x0;
+    const T hh = T(0.5) * (T(1.0) - h);
+    for (int n = 0; n < 50; ++n) {
+        T s, c;
+        sincospi_(T(2.0) * x, &s, &c);
+        const T f = T(PI_D) * x + hh * s - th;
+        const T fp = T(PI_D) * (T(1.0) + (T(1.0) - h) * c);
+        T xn;
+        if (fabs_(fp) < T(1e-300)) {
+            xn = T(0.05);
+        } else {
+            xn = x - f / fp;
+            if (xn < T(0.0) || xn > T(1.0)) xn = T(0.05);
+        }
+        const T dx = fabs_(xn - x);
+        x = xn;
+        if (dx < T(1e-14)) break;
+    }
+    return x;
+}
+
+// Bilinear combination of the four corner values of each field (weights w1 along x1, w2
+// along x2).
+template <class T>
+__host__ __device__ inline void bilerp4(const T* a, const T* b, const T* c, const T* d, T w1, T w2, T* out)
+{
+    const T u1 = T(1.0) - w1, u2 = T(1.0) - w2;
+    for (int f = 0; f < 4; ++f) out[f] = u2 * (u1 * a[f] + w1 * b[f]) + w2 * (u1 * c[f] + w1 * d[f]);
+}
+
+__device__ inline void load_cell(const DevGrid& g, int s, int j, int i, double v[4])
+{
+    const size_t idx = ((size_t)s * g.n2 + j) * g.n1 + i;
+    if (g.is_f64) {
+        const double4 q = reinterpret_cast<const double4*>(g.cells)[idx];
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        const float4 q = reinterpret_cast<const float4*>(g.cells)[idx];
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+}
+
+// Bilinear interpolation between cell centres (clamped to the edge centres in the outer
+// half cells) of snapshot s at fractional cell coordinates computed by the caller.
+__device__ inline void bilinear(const DevGrid& g, int s, int i0, int j0, double w1, double w2, double out[4])
+{
+    double a[4], b[4], c[4], d[4];
+    load_cell(g, s, j0, i0, a);
+    load_cell(g, s, j0, i0 + 1, b);
+    load_cell(g, s, j0 + 1, i0, c);
+    load_cell(g, s, j0 + 1, i0 + 1, d);
+    bilerp4(a, b, c, d, w1, w2, out);
+}
+
+// Density modulation of the synthetic time series at snapshot time ts:
+// 1 + A sum_{m=1..4} cos(m psi + phase_m), psi = phi - Omega_K ts, Omega_K = 1/(r^1.5 + a_gen),
+// with cos(m psi), sin(m psi) from the Chebyshev recurrence of one sincos.
+__device__ inline double modulation(const DevGrid& g, double r, double ph, double ts)
+{
+    if (g.mod_amp == 0.0) return 1.0;
+    const double om = 1.0 / (r * ::sqrt(r) + g.a_gen);
+    double s1, c1;
+    ::sincos(ph - om * ts, &s1, &c1);
+    double cm = c1, sm = s1, acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        acc += cm * g.mod_cos[m] - sm * g.mod_sin[m];
+        const double cn = cm * c1 - sm * s1;
+        const double sn = sm * c1 + cm * s1;
+        cm = cn;
+        sm = sn;
+    }
+    return 1.0 + g.mod_amp * acc;
+}
+
+// Fluid quantities {n_e, Theta_e, B, Omega} at the ray point; false where there is no plasma
+// (outside [r_in, r_out]).  x2 is warm-started from *x2w and returned there.
+__device__ inline bool sample_fluid(const DevGrid& g, int slow_light, int fast_snap, const double* y,
+                                    double* x2w, double out[4])
+{
+    const double r = y[1];
+    if (!(r >= g.r_in && r <= g.r_out)) return false;
+    const double x1 = ::log(r);
+    const double x2 = mks_x2(g.hslope, y[2], *x2w);
+    *x2w = x2;
+    double f1 = (x1 - g.lnr_in) * g.inv_d1 - 0.5;
+    double f2 = x2 * g.n2 - 0.5;
+    f1 = ::fmin(::fmax(f1, 0.0), (double)(g.n1 - 1));
+    f2 = ::fmin(::fmax(f2, 0.0), (double)(g.n2 - 1));
+    int i0 = (int)::floor(f1), j0 = (int)::floor(f2);
+    i0 = i0 > g.n1 - 2 ? g.n1 - 2 : i0;
+    j0 = j0 > g.n2 - 2 ? g.n2 - 2 : j0;
+    const double w1 = f1 - i0, w2 = f2 - j0;
+    int s0 = fast_snap;
+    double w = 0.0;
+    if (slow_light && g.n_snap > 1) {
+        // clamp before the conversion so that any finite time maps to a valid snapshot pair
+        const double q = ::fmin(::fmax((y[0] - g.t0) * g.inv_dt, -1.0), (double)g.n_snap);
+        s0 = (int)::floor(q);
+        s0 = s0 < 0 ? 0 : (s0 > g.n_snap - 2 ? g.n_snap - 2 : s0);
+        w = ::fmin(::fmax(q - s0, 0.0), 1.0);
+    }
+    double v0[4];
+    bilinear(g, s0, i0, j0, w1, w2, v0);
+    v0[0] *= modulation(g, r, y[3], g.t0 + s0 * g.dt_snap);
+    if (w > 0.0) {
+        double v1[4];
+        bilinear(g, s0 + 1, i0, j0, w1, w2, v1);
+        v1[0] *= modulation(g, r, y[3], g.t0 + (s0 + 1) * g.dt_snap);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) out[f] = (1.0 - w) * v0[f] + w * v1[f];
+    } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) out[f] = v0[f];
+    }
+    return true;
+}
+
+// Fluid frame of a circular flow u = u^t (1, 0, 0, Omega) in the KS metric, with the ZAMO
+// angular velocity where Omega is not timelike.  Returns nu_r = -k.u and the cosine of the
+// fluid-frame angle between k and the unit toroidal field b ~ (u_phi, 0, 0, -u_t).
+template <class T>
+__host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T omega, T* nu_r, T* cos_b)
+{
+    using namespace rt;
+    const T r = y[1];
+    T s, c;
+    sincos_(y[2], &s, &c);
+    const T s2 = s * s;
+    const T sig = r * r + a2 * c * c;
+    const T z = T(2.0) * M * r * rcp(sig);
+    const T z1 = T(1.0) + z;
+    const T gtt = z - T(1.0);
+    const T gtp = -a * z * s2;
+    const T grp = -a * s2 * z1;
+    const T gpp = s2 * (sig + a2 * s2 * z1);
+    bool zamo = false;
+    T D = -(gtt + T(2.0) * gtp * omega + gpp * omega * omega);
+    if (D <= T(1e-10)) {
+        omega = -gtp / gpp;
+        D = -(gtt + T(2.0) * gtp * omega + gpp * omega * omega);
+        zamo = true;
+    }
+    const T ut = rcp(sqrt_(D));
+    const T up = omega * ut;
+    const T u_t = gtt * ut + gtp * up;
+    const T u_p = gtp * ut + gpp * up;
+    const T kt = y[4], kr = y[5], kp = y[7];
+    const T k_t = gtt * kt + z * kr + gtp * kp;
+    const T k_p = gtp * kt + grp * kr + gpp * kp;
+    const T nr = -(k_t * ut + k_p * up);
+    const T bb = gtt * u_p * u_p - T(2.0) * gtp * u_p * u_t + gpp * u_t * u_t;
+    const T kb = (k_t * u_p - k_p * u_t) * rcp(sqrt_(bb));
+    T cb = kb / nr;
+    cb = fmin_(fmax_(cb, T(-1.0)), T(1.0));
+    *nu_r = nr;
+    *cos_b = cb;
+    return zamo;
+}
+
+// ln K2(1/Theta) from the tabulated values and u-derivatives at uniform u = ln Theta nodes,
+// cubic Hermite interpolation; u is clamped to the table range.
+__device__ inline double ln_k2(const K2Table& t, double lnth)
+{
+    double q = (lnth - t.u0) * t.inv_du;
+    q = ::fmin(::fmax(q, 0.0), (double)(t.n - 1) - 1e-9);
+    const int i = (int)q;
+    const double s = q - i;
+    const double2 A = t.tab[i], B = t.tab[i + 1];
+    const double s2 = s * s, s3 = s2 * s;
+    const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
+    const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
+    return h00 * A.x + h10 * A.y * t.du + h01 * B.x + h11 * B.y * t.du;
+}
+
+// Emission j_nu and absorption alpha_nu in the fluid frame (Sec. 4.2.2): Leung et al. fit
+// with nu_s = (2/9) nu_c Theta_e^2 sin(theta_B), X = nu/nu_s,
+// (X^1/2 + 2^11/12 X^1/6)^2 = X^1/3 (X^1/3 + 2^11/12)^2, and alpha = j / B_nu.  *bnu gets
+// B_nu (the source function j/alpha of thermal emission).  k2_inv = 1 / K2(1/Theta_e).
+template <class T>
+__host__ __device__ inline void closure_exact(T nu, T ne, T the, T bf, T sinb, T k2_inv, T* j, T* alpha, T* bnu)
+{
+    using namespace rt;
+    const T nu_s = T(2.0 / 9.0 * NUC_PER_GAUSS) * bf * the * the * sinb;
+    const T X = nu / nu_s;
+    const T t = cbrt_(X);
+    const T tc = t + T(TWO_11_12);
+    const T jv = T(J_PREF) * ne * nu_s * k2_inv * t * tc * tc * exp_(-t);
+    const T B = T(PLANCK_PREF) * nu * nu * nu / expm1_(T(H_OVER_MEC2) * nu / the);
+    *j = jv;
+    *alpha = jv / B;
+    *bnu = B;
+}
+
+// Backward formal-solution update of one frequency (Sec. 3.1): the step's emission with
+// source S = j/alpha over optical depth dtau = alpha ds, attenuated by the optical depth tau
+// already between the point and the camera, in observed units (1/nu_r^3).
+template <class T>
+__host__ __device__ inline void transfer_update(T j, T al, T S, T ds, T inr3, T& I, T& tau)
+{
+    using namespace rt;
+    const T dtau = al * ds;
+    const T att = exp_(-tau);
+    const T add = (dtau > T(0.0)) ? att * S * (-expm1_(-dtau)) * inr3 : att * j * ds * inr3;
+    I = I + add;
+    tau = tau + dtau;
+}
+
+}  // namespace pl

@@ -1,0 +1,90 @@
+// rt_math.hpp -- scalar primitives used by the device math, overloadable per number type.
+//
+// Device code instantiates the templates with double (geodesic, fluid frame) and float or
+// double (transfer).  The host instantiates them once with OpCounted to count the
+// algorithmic work of a step: +, -, * count one flop each (a fused multiply-add is written
+// as a product and a sum, so it counts two); divisions, square roots and transcendental
+// calls count as "special" operations and not as flops.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+namespace rt {
+
+// ---------------------------------------------------------------- double / float (device and host)
+__host__ __device__ inline double rcp(double x) { return 1.0 / x; }
+__host__ __device__ inline float rcp(float x) { return 1.0f / x; }
+__host__ __device__ inline double sqrt_(double x) { return ::sqrt(x); }
+__host__ __device__ inline float sqrt_(float x) { return ::sqrtf(x); }
+__host__ __device__ inline double cbrt_(double x) { return ::cbrt(x); }
+__host__ __device__ inline float cbrt_(float x) { return ::cbrtf(x); }
+__host__ __device__ inline double exp_(double x) { return ::exp(x); }
+__host__ __device__ inline float exp_(float x) { return ::expf(x); }
+__host__ __device__ inline double expm1_(double x) { return ::expm1(x); }
+__host__ __device__ inline float expm1_(float x) { return ::expm1f(x); }
+__host__ __device__ inline double log_(double x) { return ::log(x); }
+__host__ __device__ inline float log_(float x) { return ::logf(x); }
+__host__ __device__ inline double fabs_(double x) { return ::fabs(x); }
+__host__ __device__ inline float fabs_(float x) { return ::fabsf(x); }
+__host__ __device__ inline double fmin_(double a, double b) { return ::fmin(a, b); }
+__host__ __device__ inline double fmax_(double a, double b) { return ::fmax(a, b); }
+__host__ __device__ inline void sincos_(double x, double* s, double* c) { ::sincos(x, s, c); }
+__host__ __device__ inline void sincospi_(double x, double* s, double* c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    ::sincospi(x, s, c);
+#else
+    *s = std::sin(M_PI * x);
+    *c = std::cos(M_PI * x);
+#endif
+}
+__host__ __device__ inline bool finite_(double x) { return ::isfinite(x); }
+__host__ __device__ inline double val(double x) { return x; }
+
+// ---------------------------------------------------------------- operation counting (host only)
+struct OpTally {
+    double flops = 0.0, special = 0.0;
+};
+extern OpTally g_tally;
+
+struct OpCounted {
+    double v;
+    OpCounted(double x = 0.0) : v(x) {}
+};
+inline OpCounted operator+(OpCounted a, OpCounted b) { g_tally.flops += 1; return a.v + b.v; }
+inline OpCounted operator-(OpCounted a, OpCounted b) { g_tally.flops += 1; return a.v - b.v; }
+inline OpCounted operator*(OpCounted a, OpCounted b) { g_tally.flops += 1; return a.v * b.v; }
+inline OpCounted operator/(OpCounted a, OpCounted b) { g_tally.special += 1; return a.v / b.v; }
+inline OpCounted operator-(OpCounted a) { return -a.v; }
+inline OpCounted& operator+=(OpCounted& a, OpCounted b) { a = a + b; return a; }
+inline OpCounted& operator-=(OpCounted& a, OpCounted b) { a = a - b; return a; }
+inline OpCounted& operator*=(OpCounted& a, OpCounted b) { a = a * b; return a; }
+inline bool operator<(OpCounted a, OpCounted b) { return a.v < b.v; }
+inline bool operator>(OpCounted a, OpCounted b) { return a.v > b.v; }
+inline bool operator<=(OpCounted a, OpCounted b) { return a.v <= b.v; }
+inline bool operator>=(OpCounted a, OpCounted b) { return a.v >= b.v; }
+inline OpCounted rcp(OpCounted x) { g_tally.special += 1; return 1.0 / x.v; }
+inline OpCounted sqrt_(OpCounted x) { g_tally.special += 1; return std::sqrt(x.v); }
+inline OpCounted cbrt_(OpCounted x) { g_tally.special += 1; return std::cbrt(x.v); }
+inline OpCounted exp_(OpCounted x) { g_tally.special += 1; return std::exp(x.v); }
+inline OpCounted expm1_(OpCounted x) { g_tally.special += 1; return std::expm1(x.v); }
+inline OpCounted log_(OpCounted x) { g_tally.special += 1; return std::log(x.v); }
+inline OpCounted fabs_(OpCounted x) { return std::fabs(x.v); }
+inline OpCounted fmin_(OpCounted a, OpCounted b) { return std::fmin(a.v, b.v); }
+inline OpCounted fmax_(OpCounted a, OpCounted b) { return std::fmax(a.v, b.v); }
+inline void sincos_(OpCounted x, OpCounted* s, OpCounted* c)
+{
+    g_tally.special += 1;
+    *s = std::sin(x.v);
+    *c = std::cos(x.v);
+}
+inline void sincospi_(OpCounted x, OpCounted* s, OpCounted* c)
+{
+    g_tally.special += 1;
+    *s = std::sin(M_PI * x.v);
+    *c = std::cos(M_PI * x.v);
+}
+inline bool finite_(OpCounted x) { return std::isfinite(x.v); }
+inline double val(OpCounted x) { return x.v; }
+
+}  // namespace rt

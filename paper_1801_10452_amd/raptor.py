@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libraptor_hip.so (the C ABI of include/raptor.h).
+
+Argument marshalling only: every step of the ray-tracing path runs in the HIP library.
+Output buffers are numpy arrays (host mode) or torch CUDA tensors (device mode); torch
+provides device memory and the current stream.  The binding refuses to run without the
+compiled library -- there is no fallback path.
+"""
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libraptor_hip.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_RANGE = 0, -1, -2, -3, -4, -5
+F32, F64 = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+CLOSURE_EXACT, CLOSURE_K2_PAPER, CLOSURE_CONST, CLOSURE_MLP = 0, 1, 2, 3
+RAY_HORIZON, RAY_ESCAPED, RAY_MAXSTEP, RAY_NUMERIC = 1, 2, 3, 4
+MAX_NU = 32
+
+DP = C.POINTER(C.c_double)
+IP = C.POINTER(C.c_int32)
+
+
+class RaptorError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"raptor status {status}: {msg}")
+        self.status = status
+
+
+class CCamera(C.Structure):
+    _fields_ = [("spin", C.c_double), ("incl_deg", C.c_double), ("r_cam", C.c_double), ("fov_half", C.c_double),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("t_frame", C.c_double)]
+
+
+class CGridDesc(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n_snap", C.c_int32), ("dtype", C.c_int32),
+                ("r_in", C.c_double), ("r_out", C.c_double), ("hslope", C.c_double), ("a_gen", C.c_double),
+                ("t0", C.c_double), ("dt_snap", C.c_double), ("mod_amp", C.c_double), ("mod_phase", C.c_double * 4),
+                ("cells", C.c_void_p)]
+
+
+class COpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("r_stop_factor", C.c_double), ("max_steps", C.c_int32),
+                ("transfer_prec", C.c_int32), ("closure", C.c_int32), ("slow_light", C.c_int32), ("mem", C.c_int32),
+                ("reserved", C.c_int32), ("mass_msun", C.c_double), ("dist_pc", C.c_double),
+                ("const_j", C.c_double), ("const_alpha", C.c_double), ("metric_mass", C.c_double)]
+
+
+class CStats(C.Structure):
+    _fields_ = [("rays", C.c_uint64), ("ray_steps", C.c_uint64), ("samples", C.c_uint64),
+                ("n_horizon", C.c_uint64), ("n_escaped", C.c_uint64), ("n_maxstep", C.c_uint64),
+                ("n_pole", C.c_uint64), ("n_numeric", C.c_uint64), ("n_mlp_fallback", C.c_uint64),
+                ("n_zamo_fallback", C.c_uint64), ("kernel_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol include/raptor.h declares
+EXPORTS = ["raptor_create", "raptor_destroy", "raptor_last_error", "raptor_grid_upload", "raptor_grid_release",
+           "raptor_default_opts", "raptor_trace_image", "raptor_trace_spectrum", "raptor_trace_spectrum_ex",
+           "raptor_trace_batch", "raptor_work_per_unit"]
+
+_lib = None
+
+
+def lib():
+    """Load the compiled HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1801_10452_amd/build.py "
+                               "(or __graft_entry__.build()); there is no CPU fallback")
+        # torch carries its own HIP runtime (SONAME libamdhip64.so.7).  Loading it first makes
+        # the dynamic loader resolve this library's HIP dependency to that same runtime, so a
+        # process holds one HIP runtime and torch's streams and pointers are valid here.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        V = C.c_void_p
+        L.raptor_create.argtypes = [C.c_int, V, C.POINTER(V)]
+        L.raptor_destroy.argtypes = [V]
+        L.raptor_destroy.restype = None
+        L.raptor_last_error.argtypes = [V]
+        L.raptor_last_error.restype = C.c_char_p
+        L.raptor_grid_upload.argtypes = [V, C.POINTER(CGridDesc), C.POINTER(V)]
+        L.raptor_grid_release.argtypes = [V, V]
+        L.raptor_grid_release.restype = None
+        L.raptor_default_opts.argtypes = [C.POINTER(COpts)]
+        L.raptor_trace_image.argtypes = [V, C.POINTER(CCamera), V, C.POINTER(COpts), C.c_double, V, V,
+                                         C.POINTER(CStats)]
+        L.raptor_trace_spectrum.argtypes = [V, C.POINTER(CCamera), V, C.POINTER(COpts), DP, C.c_int32, V, V,
+                                            C.POINTER(CStats)]
+        L.raptor_trace_spectrum_ex.argtypes = [V, C.POINTER(CCamera), V, C.POINTER(COpts), DP, C.c_int32, V, V, V,
+                                               V, C.POINTER(CStats)]
+        L.raptor_trace_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
+                                         C.c_int32, V, V, C.POINTER(CStats)]
+        L.raptor_work_per_unit.argtypes = [DP] * 6
+        for name in EXPORTS:
+            if name not in ("raptor_destroy", "raptor_last_error", "raptor_grid_release"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> COpts:
+    o = COpts()
+    lib().raptor_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def make_camera(cam) -> CCamera:
+    return CCamera(cam.spin, cam.incl_deg, cam.r_cam, cam.fov_half, cam.nx, cam.ny, cam.t_frame)
+
+
+def work_per_unit():
+    v = [C.c_double() for _ in range(6)]
+    lib().raptor_work_per_unit(*[C.byref(x) for x in v])
+    keys = ["step_flops", "step_special", "sample_flops", "sample_special", "freq_flops", "freq_special"]
+    return {k: x.value for k, x in zip(keys, v)}
+
+
+def _ptr(a):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+@dataclass
+class GridHandle:
+    ptr: int
+    ctx: "Context"
+
+
+class Context:
+    """A raptor context on one HIP device.  stream: a hipStream_t as int (None: the context's own
+    stream, or torch's current stream when use_torch_stream=True)."""
+
+    def __init__(self, device=0, stream=None, use_torch_stream=False):
+        if use_torch_stream:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        st = lib().raptor_create(device, C.c_void_p(stream) if stream else None, C.byref(h))
+        if st != OK:
+            raise RaptorError(st, lib().raptor_last_error(None).decode())
+        self.h = h
+        self._grids = []
+
+    def close(self):
+        if self.h:
+            lib().raptor_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != OK:
+            raise RaptorError(st, lib().raptor_last_error(self.h).decode())
+
+    def upload_grid(self, g) -> GridHandle:
+        cells = np.ascontiguousarray(g.cells)
+        d = CGridDesc(g.n1, g.n2, g.n_snap, F64 if cells.dtype == np.float64 else F32, g.r_in, g.r_out, g.hslope,
+                      g.a_gen, g.t0, g.dt_snap, g.mod_amp, (C.c_double * 4)(*g.mod_phase), cells.ctypes.data)
+        h = C.c_void_p()
+        self._check(lib().raptor_grid_upload(self.h, C.byref(d), C.byref(h)))
+        gh = GridHandle(h.value, self)
+        self._grids.append(gh)
+        return gh
+
+    def release_grid(self, gh: GridHandle):
+        lib().raptor_grid_release(self.h, C.c_void_p(gh.ptr))
+
+    def trace_spectrum(self, cam, grid, nu, opts=None, images=None, flux=None, ray_status=None, ray_steps=None):
+        """Trace one image at the frequencies nu.  In host mode (opts.mem == MEM_HOST) outputs
+        are numpy arrays allocated here when not given; in device mode pass torch tensors.
+        Returns (images, flux, stats) with images [n_nu][ny][nx]."""
+        opts = opts or default_opts()
+        nu = np.ascontiguousarray(np.atleast_1d(nu), dtype=np.float64)
+        if opts.mem == MEM_HOST:
+            if images is None:
+                images = np.zeros((nu.size, cam.ny, cam.nx))
+            if flux is None:
+                flux = np.zeros(nu.size)
+        st = CStats()
+        c = make_camera(cam)
+        self._check(lib().raptor_trace_spectrum_ex(self.h, C.byref(c), C.c_void_p(grid.ptr), C.byref(opts),
+                                                   nu.ctypes.data_as(DP), nu.size, _ptr(images), _ptr(flux),
+                                                   _ptr(ray_status), _ptr(ray_steps), C.byref(st)))
+        return images, flux, st
+
+    def trace_image(self, cam, grid, nu, opts=None, image=None, flux=None):
+        opts = opts or default_opts()
+        if opts.mem == MEM_HOST:
+            if image is None:
+                image = np.zeros((cam.ny, cam.nx))
+            if flux is None:
+                flux = np.zeros(1)
+        st = CStats()
+        c = make_camera(cam)
+        self._check(lib().raptor_trace_image(self.h, C.byref(c), C.c_void_p(grid.ptr), C.byref(opts), float(nu),
+                                             _ptr(image), _ptr(flux), C.byref(st)))
+        return image, flux, st
+
+    def trace_batch(self, cams, grids, nu, opts=None, images=None, flux=None):
+        """cams: list of cameras; grids: one GridHandle per camera; nu: [n_cams][n_nu] (or one
+        list used for every camera).  images: all images concatenated, flux [n_cams][n_nu]."""
+        opts = opts or default_opts()
+        n = len(cams)
+        nu = np.asarray(nu, dtype=np.float64)
+        if nu.ndim == 1:
+            nu = np.tile(nu, (n, 1))
+        nu = np.ascontiguousarray(nu)
+        n_nu = nu.shape[1]
+        total = sum(c.nx * c.ny for c in cams) * n_nu
+        if opts.mem == MEM_HOST:
+            if images is None:
+                images = np.zeros(total)
+            if flux is None:
+                flux = np.zeros((n, n_nu))
+        carr = (CCamera * n)(*[make_camera(c) for c in cams])
+        garr = (C.c_void_p * n)(*[g.ptr for g in grids])
+        st = CStats()
+        self._check(lib().raptor_trace_batch(self.h, carr, n, garr, C.byref(opts), nu.ctypes.data_as(DP), n_nu,
+                                             _ptr(images), _ptr(flux), C.byref(st)))
+        return images, flux, st
+
+
+def split_batch_images(images, cams, n_nu):
+    """View the concatenated batch output as a list of [n_nu][ny][nx] arrays."""
+    out, o = [], 0
+    for c in cams:
+        n = n_nu * c.nx * c.ny
+        out.append(images[o:o + n].reshape(n_nu, c.ny, c.nx))
+        o += n
+    return out
