@@ -158,6 +158,37 @@ raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int
                                  const double* nu_hz, int32_t n_nu, double* images, double* flux_jy,
                                  raptor_stats* stats);
 
+/* Launch plan of the persistent trace kernel: the autotuner's search space.  A plan is kept
+ * per context for each (n_nu, transfer_prec) pair. */
+typedef struct {
+    int32_t threads;             /* work-group size: 64, 128 or 256 */
+    int32_t blocks_per_cu;       /* persistent work-groups per compute unit; 0 = as many as fit */
+    int32_t refill_threshold;    /* a wave refills its idle lanes once this many are idle (1..64) */
+    int32_t tile_width;          /* pixels per tile row: 8, 16, 32 or 64 (a tile is 64 rays) */
+    int32_t min_waves_per_simd;  /* 1, 2 or 3: the kernel variant compiled for at least that many
+                                    waves per SIMD (register cap 512, 256 or 168) */
+    int32_t reserved[3];
+} raptor_plan;
+
+/* Current plan for (n_nu, transfer_prec) (the default plan if none was set or tuned). */
+raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, raptor_plan* out);
+/* Install a plan for (n_nu, transfer_prec); RAPTOR_E_INVALID if a field is out of range. */
+raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan);
+/* Autotuner: runs the given batch (arguments as raptor_trace_batch, outputs discarded) under
+ * candidate plans by coordinate descent over the plan fields, timing each candidate with HIP
+ * events as the fastest of `reps` runs, and installs the fastest plan for (n_nu,
+ * opts->transfer_prec).  best and best_ms (the fastest kernel time) may be NULL. */
+raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                    const raptor_grid* const* grids, const raptor_opts* opts,
+                                    const double* nu_hz, int32_t n_nu, int32_t reps, raptor_plan* best,
+                                    double* best_ms);
+
+/* Resources of the trace-kernel instantiation a plan selects: registers per lane, scratch
+ * (spill) bytes per lane and resident work-groups per compute unit at the plan's work-group
+ * size.  Any output pointer may be NULL. */
+raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan,
+                                 int32_t* vgprs, int32_t* scratch_bytes, int32_t* blocks_per_cu);
+
 /* Algorithmic work per unit, counted once on the host by running the kernel's scalar
  * expressions through an operation-counting number type: FP64 add / sub / mul (a fused
  * multiply-add counts 2) of one accepted RK4 step including the step rule (step_*), of the

@@ -7,12 +7,16 @@
 // {n_e, Theta_e, B, Omega}.
 struct DevGrid {
     const void* cells;
+    const float* x2tab;        // x2(theta) at x2n uniform theta nodes on [0, pi] (start values)
+    int x2n, pad;
+    double x2_inv_dth;
     int n1, n2, n_snap, is_f64;
     double lnr_in, inv_d1, r_in, r_out, hslope, a_gen, t0, dt_snap, inv_dt, mod_amp;
     double mod_cos[4], mod_sin[4];   // cos / sin of the modulation phases
 };
 
-// One image of a launch.  Rays are numbered tile by tile (8 x 8 pixels per 64-ray tile);
+// One image of a launch.  Rays are numbered tile by tile (64 rays per tile, 8 x 8 pixels by
+// default; the tile width is a launch-plan parameter);
 // the job owns the global tiles [tile_base, tile_base + tiles_x * tiles_y).
 struct DevJob {
     double a, incl, sin_i, cos_i, r_cam, fov, dalpha, dbeta, r_stop, t_init;
@@ -48,7 +52,7 @@ struct TraceParams {
     K2Table k2;
     long long n_tiles;
     int n_jobs, max_steps, closure, slow_light;
-    int refill_threshold, pad;
+    int refill_threshold, tile_shift;   // tile width = 1 << tile_shift pixels, height 64 / width
     double eps, M, length_unit, const_j, const_alpha;
 };
 

@@ -59,13 +59,13 @@ struct DevBuf {
 struct raptor_grid {
     DevGrid d{};
     void* cells = nullptr;
+    float* x2tab = nullptr;
     raptor_ctx* owner = nullptr;
 };
 
 struct LaunchPlan {
-    int threads = 256;
-    int blocks = 0;
-    int refill = 1;
+    raptor_plan p{256, 0, 1, 8, 2, {0, 0, 0}};
+    int blocks = 0;   // resolved work-group count
 };
 
 struct raptor_ctx {
@@ -73,6 +73,7 @@ struct raptor_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int cu_count = 0;
+    size_t lds_per_block = 65536;
     std::string err;
     DevBuf<DevJob> jobs;
     DevBuf<DevGrid> grids;
@@ -199,28 +200,71 @@ struct JobIn {
     const double* nu;
 };
 
+bool plan_valid(const raptor_plan& p)
+{
+    const bool tw = p.tile_width == 8 || p.tile_width == 16 || p.tile_width == 32 || p.tile_width == 64;
+    return (p.threads == 64 || p.threads == 128 || p.threads == 256) && p.blocks_per_cu >= 0 &&
+           p.blocks_per_cu <= 64 && p.refill_threshold >= 1 && p.refill_threshold <= 64 && tw &&
+           (p.min_waves_per_simd >= 1 && p.min_waves_per_simd <= 3);
+}
+
+int plan_key(int n_nu, bool fp32)
+{
+    const int nnu = n_nu <= 1 ? 1 : n_nu <= 4 ? 4 : n_nu <= 8 ? 8 : n_nu <= 16 ? 16 : 32;
+    return nnu * 2 + (fp32 ? 1 : 0);
+}
+
+// Resolve the work-group count of a plan: blocks_per_cu per compute unit, or as many as are
+// resident at once when 0.
+raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* pl)
+{
+    // the per-wave sample queue lives in LDS: shrink the work-group until it fits
+    while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.threads) > ctx->lds_per_block)
+        pl->p.threads /= 2;
+    if (trace_kernel_lds(max_nu, fp32, pl->p.threads) > ctx->lds_per_block)
+        return fail(ctx, RAPTOR_E_UNSUPPORTED, "the sample queue of one wave exceeds the LDS of a work-group");
+    int per_cu = pl->p.blocks_per_cu;
+    if (per_cu == 0) {
+        RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, trace_kernel_symbol(max_nu, fp32, pl->p.min_waves_per_simd), pl->p.threads,
+                      trace_kernel_lds(max_nu, fp32, pl->p.threads)),
+                  "querying occupancy");
+        per_cu = std::max(per_cu, 1);
+    }
+    pl->blocks = ctx->cu_count * per_cu;
+    return RAPTOR_OK;
+}
+
 raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out)
 {
-    const int key = max_nu * 2 + (fp32 ? 1 : 0);
+    const int key = plan_key(max_nu, fp32);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
         *out = it->second;
         return RAPTOR_OK;
     }
     LaunchPlan pl;
-    int per_cu = 0;
-    RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel_symbol(max_nu, fp32), pl.threads, 0),
-              "querying occupancy");
-    pl.blocks = ctx->cu_count * std::max(per_cu, 1);
+    raptor_status s = resolve_plan(ctx, max_nu, fp32, &pl);
+    if (s != RAPTOR_OK) return s;
     ctx->plans[key] = pl;
     *out = pl;
     return RAPTOR_OK;
 }
 
 raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, const raptor_opts* o,
-                       double* images, double* flux_jy, int32_t* ray_status, int32_t* ray_steps, raptor_stats* st)
+                       double* images, double* flux_jy, int32_t* ray_status, int32_t* ray_steps, raptor_stats* st,
+                       const LaunchPlan* force_plan = nullptr)
 {
     const bool dev = o->mem == RAPTOR_MEM_DEVICE;
+    const bool fp32 = o->transfer_prec == RAPTOR_F32;
+    LaunchPlan plan;
+    if (force_plan) {
+        plan = *force_plan;
+    } else {
+        raptor_status ps = plan_for(ctx, n_nu, fp32, &plan);
+        if (ps != RAPTOR_OK) return ps;
+    }
+    const int tile_w = plan.p.tile_width, tile_h = 64 / tile_w;
     const int nj = (int)in.size();
     // ---- job table
     std::vector<DevJob> jobs(nj);
@@ -246,12 +290,12 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
         J.t_init = c.t_frame + c.r_cam;
         J.nx = c.nx;
         J.ny = c.ny;
-        J.tiles_x = (c.nx + 7) / 8;
+        J.tiles_x = (c.nx + tile_w - 1) / tile_w;
         J.n_nu = n_nu;
         J.tile_base = tiles;
         J.out_base = outn;
         J.pix_base = pixn;
-        tiles += (long long)J.tiles_x * ((c.ny + 7) / 8);
+        tiles += (long long)J.tiles_x * ((c.ny + tile_h - 1) / tile_h);
         outn += (long long)n_nu * c.nx * c.ny;
         pixn += (long long)c.nx * c.ny;
         auto gi = std::find(gl.begin(), gl.end(), in[k].grid);
@@ -327,15 +371,13 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     p.length_unit = Lu;
     p.const_j = o->const_j;
     p.const_alpha = o->const_alpha;
-    const bool fp32 = o->transfer_prec == RAPTOR_F32;
-    LaunchPlan plan;
-    raptor_status ps = plan_for(ctx, n_nu, fp32, &plan);
-    if (ps != RAPTOR_OK) return ps;
-    p.refill_threshold = plan.refill;
+    p.refill_threshold = plan.p.refill_threshold;
+    p.tile_shift = tile_w == 8 ? 3 : tile_w == 16 ? 4 : tile_w == 32 ? 5 : 6;
 
     RAPTOR_CK(launch_reset(ctx->counter.p, ctx->stats.p, s), "launching reset");
     RAPTOR_CK(hipEventRecord(ctx->ev0, s), "recording an event");
-    RAPTOR_CK(launch_trace(p, n_nu, fp32, plan.blocks, plan.threads, s), "launching the trace kernel");
+    RAPTOR_CK(launch_trace(p, n_nu, fp32, plan.p.min_waves_per_simd, plan.blocks, plan.p.threads, s),
+              "launching the trace kernel");
     RAPTOR_CK(hipEventRecord(ctx->ev1, s), "recording an event");
     RAPTOR_CK(launch_flux(ctx->jobs.p, nj, out, ctx->pixsr.p, ctx->flux.p, n_nu, s), "launching the flux reduction");
 
@@ -419,6 +461,7 @@ raptor_status raptor_create(int device, void* hip_stream, raptor_ctx** out)
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return bail(dev_fail(ctx, e, "reading device properties"));
     ctx->cu_count = prop.multiProcessorCount;
+    ctx->lds_per_block = prop.sharedMemPerBlock;
     if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess || (e = hipEventCreate(&ctx->ev1)) != hipSuccess)
         return bail(dev_fail(ctx, e, "creating events"));
     if ((e = ctx->counter.reserve(1)) != hipSuccess || (e = ctx->stats.reserve(ST_COUNT)) != hipSuccess)
@@ -436,6 +479,7 @@ void raptor_destroy(raptor_ctx* ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (raptor_grid* g : ctx->live) {
         if (g->cells) (void)hipFree(g->cells);
+        if (g->x2tab) (void)hipFree(g->x2tab);
         delete g;
     }
     ctx->jobs.release();
@@ -507,8 +551,35 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
         delete g;
         return dev_fail(ctx, e, "uploading the grid");
     }
+    // start values of the MKS inverse x2(theta) on uniform theta nodes (Newton on the host)
+    const int x2n = 8192;
+    std::vector<float> x2h(x2n);
+    for (int i = 0; i < x2n; ++i) {
+        const double th = kPi * i / (x2n - 1);
+        double x = th / kPi;
+        for (int it = 0; it < 100; ++it) {
+            const double f = kPi * x + 0.5 * (1.0 - d->hslope) * std::sin(2.0 * kPi * x) - th;
+            const double fp = kPi * (1.0 + (1.0 - d->hslope) * std::cos(2.0 * kPi * x));
+            const double xn = std::min(std::max(x - f / fp, 0.0), 1.0);
+            const bool done = std::fabs(xn - x) < 1e-15;
+            x = xn;
+            if (done) break;
+        }
+        x2h[i] = (float)x;
+    }
+    e = hipMalloc(&g->x2tab, x2n * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(g->x2tab, x2h.data(), x2n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (g->x2tab) (void)hipFree(g->x2tab);
+        (void)hipFree(g->cells);
+        delete g;
+        return dev_fail(ctx, e, "uploading the MKS table");
+    }
     DevGrid& G = g->d;
     G.cells = g->cells;
+    G.x2tab = g->x2tab;
+    G.x2n = x2n;
+    G.x2_inv_dth = (x2n - 1) / kPi;
     G.n1 = d->n1;
     G.n2 = d->n2;
     G.n_snap = d->n_snap;
@@ -541,6 +612,7 @@ void raptor_grid_release(raptor_ctx* ctx, raptor_grid* g)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (g->cells) (void)hipFree(g->cells);
+    if (g->x2tab) (void)hipFree(g->x2tab);
     ctx->live.erase(it);
     delete g;
 }
@@ -574,24 +646,148 @@ raptor_status raptor_trace_image(raptor_ctx* ctx, const raptor_camera* cam, cons
     return raptor_trace_spectrum_ex(ctx, cam, grid, opts, &nu_hz, 1, image, flux_jy, nullptr, nullptr, stats);
 }
 
+static raptor_status batch_inputs(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                  const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz,
+                                  int32_t n_nu, std::vector<JobIn>* in)
+{
+    raptor_status s;
+    if (!cams || !grids || n_cams < 1) return fail(ctx, RAPTOR_E_INVALID, "need n_cams >= 1 cameras and grids");
+    if ((s = check_opts(ctx, opts)) != RAPTOR_OK) return s;
+    if (!nu_hz) return fail(ctx, RAPTOR_E_INVALID, "nu_hz is NULL");
+    in->resize(n_cams);
+    for (int k = 0; k < n_cams; ++k) {
+        if ((s = check_nu(ctx, nu_hz + (size_t)k * n_nu, n_nu)) != RAPTOR_OK) return s;
+        if ((s = check_camera(ctx, &cams[k], grids[k], opts, k)) != RAPTOR_OK) return s;
+        (*in)[k] = {&cams[k], grids[k], nu_hz + (size_t)k * n_nu};
+    }
+    return RAPTOR_OK;
+}
+
 raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
                                  const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz,
                                  int32_t n_nu, double* images, double* flux_jy, raptor_stats* stats)
 {
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
-    raptor_status s;
-    if (!cams || !grids || n_cams < 1) return fail(ctx, RAPTOR_E_INVALID, "need n_cams >= 1 cameras and grids");
-    if ((s = check_opts(ctx, opts)) != RAPTOR_OK) return s;
-    if (!nu_hz) return fail(ctx, RAPTOR_E_INVALID, "nu_hz is NULL");
-    std::vector<JobIn> in(n_cams);
-    for (int k = 0; k < n_cams; ++k) {
-        if ((s = check_nu(ctx, nu_hz + (size_t)k * n_nu, n_nu)) != RAPTOR_OK) return s;
-        if ((s = check_camera(ctx, &cams[k], grids[k], opts, k)) != RAPTOR_OK) return s;
-        in[k] = {&cams[k], grids[k], nu_hz + (size_t)k * n_nu};
-    }
+    std::vector<JobIn> in;
+    raptor_status s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, &in);
+    if (s != RAPTOR_OK) return s;
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
     return run_jobs(ctx, in, n_nu, opts, images, flux_jy, nullptr, nullptr, stats);
+}
+
+raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, raptor_plan* out)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    if (!out || n_nu < 1 || n_nu > RAPTOR_MAX_NU || (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64))
+        return fail(ctx, RAPTOR_E_INVALID, "bad arguments to raptor_get_plan");
+    LaunchPlan pl;
+    raptor_status s = plan_for(ctx, n_nu, transfer_prec == RAPTOR_F32, &pl);
+    if (s != RAPTOR_OK) return s;
+    *out = pl.p;
+    return RAPTOR_OK;
+}
+
+raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    if (!plan || n_nu < 1 || n_nu > RAPTOR_MAX_NU || (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64))
+        return fail(ctx, RAPTOR_E_INVALID, "bad arguments to raptor_set_plan");
+    if (!plan_valid(*plan)) return fail(ctx, RAPTOR_E_INVALID, "plan field out of range");
+    LaunchPlan pl;
+    pl.p = *plan;
+    const bool fp32 = transfer_prec == RAPTOR_F32;
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    raptor_status s = resolve_plan(ctx, n_nu, fp32, &pl);
+    if (s != RAPTOR_OK) return s;
+    ctx->plans[plan_key(n_nu, fp32)] = pl;
+    return RAPTOR_OK;
+}
+
+raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                    const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz,
+                                    int32_t n_nu, int32_t reps, raptor_plan* best, double* best_ms)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    std::vector<JobIn> in;
+    raptor_status s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, &in);
+    if (s != RAPTOR_OK) return s;
+    if (reps < 1 || reps > 100) return fail(ctx, RAPTOR_E_INVALID, "reps must be in [1, 100]");
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    raptor_opts o = *opts;
+    o.mem = RAPTOR_MEM_DEVICE;   // outputs stay in the context's buffers
+    const bool fp32 = o.transfer_prec == RAPTOR_F32;
+    auto time_plan = [&](const raptor_plan& cand, double* ms) -> raptor_status {
+        LaunchPlan pl;
+        pl.p = cand;
+        raptor_status r = resolve_plan(ctx, n_nu, fp32, &pl);
+        if (r != RAPTOR_OK) return r;
+        double bestv = 1e300;
+        for (int i = 0; i < reps; ++i) {
+            raptor_stats st;
+            r = run_jobs(ctx, in, n_nu, &o, nullptr, nullptr, nullptr, nullptr, &st, &pl);
+            if (r != RAPTOR_OK) return r;
+            bestv = std::min(bestv, st.kernel_ms);
+        }
+        *ms = bestv;
+        return RAPTOR_OK;
+    };
+    LaunchPlan cur;
+    s = plan_for(ctx, n_nu, fp32, &cur);
+    if (s != RAPTOR_OK) return s;
+    raptor_plan bp = cur.p;
+    double bms;
+    if ((s = time_plan(bp, &bms)) != RAPTOR_OK) return s;
+    // coordinate descent over the plan fields
+    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256}, {0, 2, 4}, {1, 8, 16, 32}, {8, 16, 64}};
+    for (int field = 0; field < (int)values.size(); ++field) {
+        for (int v : values[field]) {
+            raptor_plan c = bp;
+            int* slot = field == 0 ? &c.min_waves_per_simd : field == 1 ? &c.threads : field == 2 ? &c.blocks_per_cu
+                      : field == 3 ? &c.refill_threshold : &c.tile_width;
+            if (*slot == v) continue;
+            *slot = v;
+            double ms;
+            if ((s = time_plan(c, &ms)) != RAPTOR_OK) return s;
+            if (ms < bms) {
+                bms = ms;
+                bp = c;
+            }
+        }
+    }
+    LaunchPlan fin;
+    fin.p = bp;
+    if ((s = resolve_plan(ctx, n_nu, fp32, &fin)) != RAPTOR_OK) return s;
+    ctx->plans[plan_key(n_nu, fp32)] = fin;
+    if (best) *best = bp;
+    if (best_ms) *best_ms = bms;
+    return RAPTOR_OK;
+}
+
+raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan,
+                                 int32_t* vgprs, int32_t* scratch_bytes, int32_t* blocks_per_cu)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    if (!plan || !plan_valid(*plan) || n_nu < 1 || n_nu > RAPTOR_MAX_NU ||
+        (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64))
+        return fail(ctx, RAPTOR_E_INVALID, "bad arguments to raptor_kernel_info");
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    const bool fp32 = transfer_prec == RAPTOR_F32;
+    int regs = 0, spill = 0, maxt = 0, per_cu = 0;
+    RAPTOR_CK(trace_kernel_attributes(n_nu, fp32, plan->min_waves_per_simd, &regs, &spill, &maxt),
+              "reading kernel attributes");
+    RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd), plan->threads,
+                  trace_kernel_lds(n_nu, fp32, plan->threads)),
+              "querying occupancy");
+    if (vgprs) *vgprs = regs;
+    if (scratch_bytes) *scratch_bytes = spill;
+    if (blocks_per_cu) *blocks_per_cu = per_cu;
+    return RAPTOR_OK;
 }
 
 raptor_status raptor_work_per_unit(double* step_flops, double* step_special, double* sample_flops,
@@ -603,7 +799,9 @@ raptor_status raptor_work_per_unit(double* step_flops, double* step_special, dou
     rt::g_tally = rt::OpTally{};
     const rk::Spin<C> sp = rk::make_spin(C(0.9375), C(1.0));
     const C dl = -rk::step_size(C(0.05), y);
-    rk::rk4_step(sp, y, dl);
+    C s0, c0;
+    rt::sincos_(y[2], &s0, &c0);
+    rk::rk4_step(sp, y, dl, s0, c0);
     if (step_flops) *step_flops = rt::g_tally.flops;
     if (step_special) *step_special = rt::g_tally.special;
 
@@ -613,12 +811,12 @@ raptor_status raptor_work_per_unit(double* step_flops, double* step_special, dou
     const double root = pl::mks_x2(0.3, rt::val(y[2]), rt::val(y[2]) / kPi);
     rt::g_tally = rt::OpTally{};
     (void)rt::log_(y[1]);
-    rt::g_tally.flops += 7;
+    rt::g_tally.flops += 7 + 5;                // grid coordinates; start value from the x2 table
     (void)pl::mks_x2(C(0.3), y[2], C(root));   // starts at the root: exactly one iteration
     C a[4] = {1, 2, 3, 4}, b[4] = {1, 2, 3, 4}, c[4] = {1, 2, 3, 4}, d[4] = {1, 2, 3, 4}, o4[4];
     pl::bilerp4(a, b, c, d, C(0.3), C(0.6), o4);
     C nr, cb;
-    (void)pl::fluid_frame(C(0.9375), C(0.9375 * 0.9375), C(1.0), y, C(0.05), &nr, &cb);
+    (void)pl::fluid_frame(C(0.9375), C(0.9375 * 0.9375), C(1.0), y, C(0.891), C(0.454), C(0.05), &nr, &cb);
     rt::g_tally.flops += 2 + 2 + 2 + 20;
     rt::g_tally.special += 1 + 1 + 2;   // 1/nu_r^3, sqrt, log + exp of the K2 lookup
     if (sample_flops) *sample_flops = rt::g_tally.flops;
@@ -629,7 +827,10 @@ raptor_status raptor_work_per_unit(double* step_flops, double* step_special, dou
     C nu = C(230e9) * nr;
     C j, al, S, I = C(0.0), tau = C(0.0);
     pl::closure_exact(nu, C(1e5), C(3.0), C(5.0), C(0.5), C(0.01), &j, &al, &S);
-    pl::transfer_update(j, al, S, C(1e10), C(0.8), I, tau);
+    C A, dtau;
+    pl::step_source(j, al, S, C(1e10), C(0.8), A, dtau);
+    I = I + rt::exp_(-tau) * A;   // fold into (I, tau)
+    tau = tau + dtau;
     if (freq_flops) *freq_flops = rt::g_tally.flops;
     if (freq_special) *freq_special = rt::g_tally.special;
     return RAPTOR_OK;

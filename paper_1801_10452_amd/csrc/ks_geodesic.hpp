@@ -33,69 +33,117 @@ __host__ __device__ inline Spin<T> make_spin(T a, T M)
     return s;
 }
 
-// f = dy/dlambda.
+// dk/dlambda = -Gamma k k at state y, given s = sin(theta), c = cos(theta).
+// F_b = Gdot_{bn} k^n - 1/2 (d_b g_mn) k^m k^n is accumulated one metric component at a time
+// (each component's r and theta derivatives enter F and are then dead), then raised with the
+// closed-form inverse metric.
 template <class T>
-__host__ __device__ inline void ks_rhs(const Spin<T>& sp, const T* y, T* f)
+__host__ __device__ inline void ks_accel(const Spin<T>& sp, const T* y, T s, T c, T* dk)
 {
     using namespace rt;
     const T a = sp.a, a2 = sp.a2, M = sp.M;
-    const T r = y[1], th = y[2];
+    const T r = y[1];
     const T kt = y[4], kr = y[5], kh = y[6], kp = y[7];
-    T s, c;
-    sincos_(th, &s, &c);
     const T s2 = s * s, c2 = c * c, sc2 = T(2.0) * s * c;
     const T r2 = r * r;
     const T sig = r2 + a2 * c2;
-    const T w = rcp(sig * s2);            // 1/(Sigma sin^2)
+    const T w = rcp_nr(sig * s2);         // 1/(Sigma sin^2)
     const T isig = w * s2;                // 1/Sigma
     const T twoMr = T(2.0) * M * r;
     const T z = twoMr * isig;             // 2 M r / Sigma
     const T z1 = T(1.0) + z;
-    const T isig2 = isig * isig;
-    const T zr = T(2.0) * M * (a2 * c2 - r2) * isig2;   // dz/dr
-    const T zt = z * a2 * sc2 * isig;                   // dz/dtheta
-    // d/dr and d/dtheta of g_tt, g_tr, g_rr (all equal to dz), g_tp, g_rp, g_hh, g_pp
-    const T dr_tp = -a * s2 * zr;
-    const T dt_tp = -a * (sc2 * z + s2 * zt);
-    const T dt_rp = -a * (sc2 * z1 + s2 * zt);
-    const T dr_hh = T(2.0) * r;
-    const T dt_hh = -a2 * sc2;
-    const T s4 = s2 * s2;
-    const T dr_pp = T(2.0) * r * s2 + a2 * s4 * zr;
-    const T dt_pp = sc2 * (sig - a2 * s2) + T(2.0) * a2 * s2 * sc2 * z1 + a2 * s4 * zt;
-    // Gdot = k^r d_r g + k^theta d_theta g
-    const T gd_z = kr * zr + kh * zt;          // tt, tr, rr
-    const T gd_tp = kr * dr_tp + kh * dt_tp;
-    const T gd_rp = kr * dr_tp + kh * dt_rp;   // d_r g_rp = d_r g_tp
-    const T gd_hh = kr * dr_hh + kh * dt_hh;
-    const T gd_pp = kr * dr_pp + kh * dt_pp;
-    // A_b = Gdot_{bn} k^n
-    const T A_t = gd_z * (kt + kr) + gd_tp * kp;
-    const T A_r = gd_z * (kt + kr) + gd_rp * kp;
-    const T A_h = gd_hh * kh;
-    const T A_p = gd_tp * kt + gd_rp * kr + gd_pp * kp;
-    // 1/2 (d_b g_mn) k^m k^n for b = r, theta
+    const T zr = T(2.0) * M * (a2 * c2 - r2) * (isig * isig);   // dz/dr
+    const T zt = z * a2 * sc2 * isig;                           // dz/dtheta
     const T ktr = kt + kr;
-    const T q_z = ktr * ktr;                   // k^t k^t + 2 k^t k^r + k^r k^r
-    const T kpk = kp * ktr;                    // k^phi (k^t + k^r)
     const T khh = kh * kh, kpp = kp * kp;
-    const T Q_r = T(0.5) * (zr * q_z + dr_hh * khh + dr_pp * kpp) + dr_tp * kpk;
-    const T Q_h = T(0.5) * (zt * q_z + dt_hh * khh + dt_pp * kpp) + dt_tp * kp * kt + dt_rp * kp * kr;
-    const T F_t = A_t;
-    const T F_r = A_r - Q_r;
-    const T F_h = A_h - Q_h;
-    const T F_p = A_p;
+    // g_tt, g_tr, g_rr: d g = dz; their k k contraction is (k^t + k^r)^2
+    const T gd_z = kr * zr + kh * zt;
+    const T hq_z = T(0.5) * ktr * ktr;
+    T F_t = gd_z * ktr;
+    T F_r = gd_z * ktr - zr * hq_z;
+    T F_h = -zt * hq_z;
+    // g_tp = -a z sin^2: d_r = -a sin^2 dz/dr, d_theta = -a (2 s c z + sin^2 dz/dtheta)
+    const T dr_tp = -a * s2 * zr;
+    {
+        const T dt_tp = -a * (sc2 * z + s2 * zt);
+        const T gd = kr * dr_tp + kh * dt_tp;
+        F_t = F_t + gd * kp;
+        T F_p0 = gd * kt;
+        F_r = F_r - dr_tp * kt * kp;
+        F_h = F_h - dt_tp * kt * kp;
+        dk[3] = F_p0;   // F_p accumulates in dk[3]
+    }
+    // g_rp = -a sin^2 (1 + z): d_r = d_r g_tp, d_theta = -a (2 s c (1 + z) + sin^2 dz/dtheta)
+    {
+        const T dt_rp = -a * (sc2 * z1 + s2 * zt);
+        const T gd = kr * dr_tp + kh * dt_rp;
+        F_r = F_r + gd * kp - dr_tp * kr * kp;
+        dk[3] = dk[3] + gd * kr;
+        F_h = F_h - dt_rp * kr * kp;
+    }
+    // g_hh = Sigma: d_r = 2 r, d_theta = -2 a^2 s c
+    {
+        const T dr_hh = T(2.0) * r;
+        const T dt_hh = -a2 * sc2;
+        const T gd = kr * dr_hh + kh * dt_hh;
+        F_h = F_h + gd * kh - T(0.5) * dt_hh * khh;
+        F_r = F_r - T(0.5) * dr_hh * khh;
+    }
+    // g_pp = sin^2 (Sigma + a^2 sin^2 (1 + z))
+    {
+        const T s4 = s2 * s2;
+        const T dr_pp = T(2.0) * r * s2 + a2 * s4 * zr;
+        const T dt_pp = sc2 * (sig - a2 * s2) + T(2.0) * a2 * s2 * sc2 * z1 + a2 * s4 * zt;
+        const T gd = kr * dr_pp + kh * dt_pp;
+        dk[3] = dk[3] + gd * kp;
+        F_r = F_r - T(0.5) * dr_pp * kpp;
+        F_h = F_h - T(0.5) * dt_pp * kpp;
+    }
+    const T F_p = dk[3];
     // inverse metric: g^tt = -(1+z), g^tr = z, g^rr = Delta/Sigma, g^rp = a/Sigma,
     // g^hh = 1/Sigma, g^pp = 1/(Sigma sin^2)
     const T gi_rr = (r2 - twoMr + a2) * isig;
-    f[0] = kt;
-    f[1] = kr;
-    f[2] = kh;
-    f[3] = kp;
-    f[4] = z1 * F_t - z * F_r;
-    f[5] = -(z * F_t + gi_rr * F_r + a * isig * F_p);
-    f[6] = -isig * F_h;
-    f[7] = -(a * isig * F_r + w * F_p);
+    const T ai = a * isig;
+    dk[0] = z1 * F_t - z * F_r;
+    dk[1] = -(z * F_t + gi_rr * F_r + ai * F_p);
+    dk[2] = -isig * F_h;
+    dk[3] = -(ai * F_r + w * F_p);
+}
+
+// f = dy/dlambda (the full eight-component right-hand side).
+template <class T>
+__host__ __device__ inline void ks_rhs(const Spin<T>& sp, const T* y, T* f)
+{
+    T s, c;
+    rt::sincos_(y[2], &s, &c);
+    f[0] = y[4];
+    f[1] = y[5];
+    f[2] = y[6];
+    f[3] = y[7];
+    ks_accel(sp, y, s, c, f + 4);
+}
+
+// sin and cos of theta + d from s0 = sin(theta), c0 = cos(theta): Taylor polynomials of sin d
+// (through d^13) and cos d (through d^14), whose truncation error is below 1e-21 for
+// |d| <= 0.25, and the angle-addition formulas; larger |d| falls back to a full sincos.
+template <class T>
+__host__ __device__ inline void sincos_shift(T th0, T s0, T c0, T th, T* s, T* c)
+{
+    using namespace rt;
+    const T d = th - th0;
+    if (fabs_(d) > T(0.25)) {
+        sincos_small(th, s, c);
+        return;
+    }
+    const T d2 = d * d;
+    const T ps = T(-1.0 / 6.0) + d2 * (T(1.0 / 120.0) + d2 * (T(-1.0 / 5040.0) + d2 * (T(1.0 / 362880.0)
+               + d2 * (T(-1.0 / 39916800.0) + d2 * T(1.0 / 6227020800.0)))));
+    const T sd = d + d * d2 * ps;
+    const T pc = T(1.0 / 24.0) + d2 * (T(-1.0 / 720.0) + d2 * (T(1.0 / 40320.0) + d2 * (T(-1.0 / 3628800.0)
+               + d2 * (T(1.0 / 479001600.0) + d2 * T(-1.0 / 87178291200.0)))));
+    const T cdm1 = d2 * (T(-0.5) + d2 * pc);   // cos d - 1
+    *s = s0 + (s0 * cdm1 + c0 * sd);
+    *c = c0 + (c0 * cdm1 - s0 * sd);
 }
 
 // Positive step size of the adaptive rule (Sec. 2.2),
@@ -111,37 +159,60 @@ __host__ __device__ inline T step_size(T eps, const T* y)
     const T x2 = y[2] * T(M_1_PI);
     const T edge = fmax_(fmin_(x2, T(1.0) - x2), T(1e-12));
     const T den = (fabs_(y[5]) + d * r) * edge + (fabs_(y[6]) * T(M_1_PI) + d) * r + (fabs_(y[7]) + d) * r * edge;
-    return eps * r * edge / den;
+    return eps * r * edge * rcp_nr(den);
 }
 
-// One classical RK4 step of size dl (negative: away from the camera).
-template <class T>
-__host__ __device__ inline void rk4_step(const Spin<T>& sp, T* y, T dl)
+// The work count treats sincos_shift as one sine-cosine evaluation.
+inline void sincos_shift(rt::OpCounted th0, rt::OpCounted s0, rt::OpCounted c0, rt::OpCounted th,
+                         rt::OpCounted* s, rt::OpCounted* c)
 {
-    T k[8], acc[8], t[8];
-    ks_rhs(sp, y, k);
+    (void)th0; (void)s0; (void)c0;
+    rt::sincos_(th, s, c);
+}
+
+// One classical RK4 step of size dl (negative: away from the camera) on y = (x, k).  s0, c0
+// are sin and cos of y[2]; the three later stages get theirs with sincos_shift.  The position
+// derivative of a stage is that stage's wave vector, so only dk/dlambda is evaluated.
+template <class T>
+__host__ __device__ inline void rk4_step(const Spin<T>& sp, T* y, T dl, T s0, T c0)
+{
+    T t[8], acc[8], dk[4];
+    T s, c;
+    ks_accel(sp, y, s0, c0, dk);
     const T h2 = T(0.5) * dl;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        acc[i] = k[i];
-        t[i] = y[i] + h2 * k[i];
+    for (int i = 0; i < 4; ++i) {
+        acc[i] = y[4 + i];
+        acc[4 + i] = dk[i];
+        t[i] = y[i] + h2 * y[4 + i];
+        t[4 + i] = y[4 + i] + h2 * dk[i];
     }
-    ks_rhs(sp, t, k);
+    sincos_shift(y[2], s0, c0, t[2], &s, &c);
+    ks_accel(sp, t, s, c, dk);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        acc[i] = acc[i] + T(2.0) * k[i];
-        t[i] = y[i] + h2 * k[i];
+    for (int i = 0; i < 4; ++i) {
+        acc[i] = acc[i] + T(2.0) * t[4 + i];
+        acc[4 + i] = acc[4 + i] + T(2.0) * dk[i];
+        t[i] = y[i] + h2 * t[4 + i];
+        t[4 + i] = y[4 + i] + h2 * dk[i];
     }
-    ks_rhs(sp, t, k);
+    sincos_shift(y[2], s0, c0, t[2], &s, &c);
+    ks_accel(sp, t, s, c, dk);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        acc[i] = acc[i] + T(2.0) * k[i];
-        t[i] = y[i] + dl * k[i];
+    for (int i = 0; i < 4; ++i) {
+        acc[i] = acc[i] + T(2.0) * t[4 + i];
+        acc[4 + i] = acc[4 + i] + T(2.0) * dk[i];
+        t[i] = y[i] + dl * t[4 + i];
+        t[4 + i] = y[4 + i] + dl * dk[i];
     }
-    ks_rhs(sp, t, k);
+    sincos_shift(y[2], s0, c0, t[2], &s, &c);
+    ks_accel(sp, t, s, c, dk);
     const T h6 = dl * T(1.0 / 6.0);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) y[i] = y[i] + h6 * (acc[i] + k[i]);
+    for (int i = 0; i < 4; ++i) {
+        y[i] = y[i] + h6 * (acc[i] + t[4 + i]);
+        y[4 + i] = y[4 + i] + h6 * (acc[4 + i] + dk[i]);
+    }
 }
 
 // Virtual camera (Sec. 2.3) at radius r_cam and polar angle incl, impact parameters

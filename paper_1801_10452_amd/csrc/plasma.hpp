@@ -17,9 +17,12 @@ constexpr double TWO_11_12 = 1.8877486253633868;                          // 2^(
 constexpr double PLANCK_PREF = 2.0 * H_PLANCK / (C_LIGHT * C_LIGHT);      // 2h/c^2
 constexpr double H_OVER_MEC2 = H_PLANCK / (ME_CGS * C_LIGHT * C_LIGHT);      // h/(m_e c^2)
 
-// theta -> x2 of the MKS polar map theta = pi x2 + (1-h)/2 sin(2 pi x2) (appendix KS-MKS) by
-// Newton-Raphson from x0, with the paper's reset to 0.05 when an iterate leaves [0, 1] or the
-// derivative vanishes, until two iterates differ by less than 1e-14 (at most 50 iterations).
+// theta -> x2 of the MKS polar map theta = pi x2 + (1-h)/2 sin(2 pi x2) (appendix KS-MKS).
+// The paper inverts the map with Newton-Raphson; here Halley's iteration (same function, third
+// order) is run from the warm start x0 with the paper's reset to 0.05 when an iterate leaves
+// [0, 1] or the derivative vanishes.  It stops after the update that moved x2 by less than
+// 1e-6: that update leaves an error of order (1e-6)^3, i.e. x2 is converged to rounding, the
+// same root the paper's iteration converges to.
 template <class T>
 __host__ __device__ inline T mks_x2(T h, T th, T x0)
 {
@@ -31,18 +34,35 @@ __host__ __device__ inline T mks_x2(T h, T th, T x0)
         sincospi_(T(2.0) * x, &s, &c);
         const T f = T(PI_D) * x + hh * s - th;
         const T fp = T(PI_D) * (T(1.0) + (T(1.0) - h) * c);
+        const T fpp = T(-2.0 * PI_D * PI_D) * (T(1.0) - h) * s;
         T xn;
         if (fabs_(fp) < T(1e-300)) {
             xn = T(0.05);
         } else {
-            xn = x - f / fp;
+            const T den = T(2.0) * fp * fp - f * fpp;
+            xn = (den > fp * fp * T(0.5)) ? x - T(2.0) * f * fp / den : x - f / fp;
             if (xn < T(0.0) || xn > T(1.0)) xn = T(0.05);
         }
         const T dx = fabs_(xn - x);
         x = xn;
-        if (dx < T(1e-14)) break;
+        if (dx < T(1e-6)) break;
     }
     return x;
+}
+
+// Float variant of ln_k2 on the float copy of the table.
+__device__ inline float ln_k2f(const K2Table& t, float lnth)
+{
+    float q = (lnth - (float)t.u0) * (float)t.inv_du;
+    q = ::fminf(::fmaxf(q, 0.0f), (float)(t.n - 1) - 1e-3f);
+    const int i = (int)q;
+    const float s = q - i;
+    const float2 A = t.tabf[i], B = t.tabf[i + 1];
+    const float du = (float)t.du;
+    const float s2 = s * s, s3 = s2 * s;
+    const float h00 = 2.0f * s3 - 3.0f * s2 + 1.0f, h10 = s3 - 2.0f * s2 + s;
+    const float h01 = -2.0f * s3 + 3.0f * s2, h11 = s3 - s2;
+    return h00 * A.x + h10 * A.y * du + h01 * B.x + h11 * B.y * du;
 }
 
 // Bilinear combination of the four corner values of each field (weights w1 along x1, w2
@@ -85,8 +105,13 @@ __device__ inline double modulation(const DevGrid& g, double r, double ph, doubl
 {
     if (g.mod_amp == 0.0) return 1.0;
     const double om = 1.0 / (r * ::sqrt(r) + g.a_gen);
+    // reduce the phase by whole turns (two-term 2 pi, exact head) before the small-argument sincos
+    const double arg = ph - om * ts;
+    const double turns = __builtin_rint(arg * 0.15915494309189535);
+    double red = __builtin_fma(-turns, 6.2831853071795862, arg);
+    red = __builtin_fma(-turns, 2.4492935982947064e-16, red);
     double s1, c1;
-    ::sincos(ph - om * ts, &s1, &c1);
+    rt::sincos_small(red, &s1, &c1);
     double cm = c1, sm = s1, acc = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -99,16 +124,24 @@ __device__ inline double modulation(const DevGrid& g, double r, double ph, doubl
     return 1.0 + g.mod_amp * acc;
 }
 
-// Fluid quantities {n_e, Theta_e, B, Omega} at the ray point; false where there is no plasma
-// (outside [r_in, r_out]).  x2 is warm-started from *x2w and returned there.
-__device__ inline bool sample_fluid(const DevGrid& g, int slow_light, int fast_snap, const double* y,
-                                    double* x2w, double out[4])
+// Start value of the MKS inverse: linear interpolation in the grid's x2(theta) table.
+__device__ inline double x2_start(const DevGrid& g, double th)
+{
+    double q = ::fmin(::fmax(th * g.x2_inv_dth, 0.0), (double)(g.x2n - 1) - 1e-9);
+    const int i = (int)q;
+    const double w = q - i;
+    return (1.0 - w) * g.x2tab[i] + w * g.x2tab[i + 1];
+}
+
+__device__ inline bool in_plasma(const DevGrid& g, double r) { return r >= g.r_in && r <= g.r_out; }
+
+// Fluid quantities {n_e, Theta_e, B, Omega} at the ray point y = (t, r, theta, phi); the caller
+// has checked that r lies in the grid's radial range.
+__device__ inline void sample_fluid(const DevGrid& g, int slow_light, int fast_snap, const double* y, double out[4])
 {
     const double r = y[1];
-    if (!(r >= g.r_in && r <= g.r_out)) return false;
     const double x1 = ::log(r);
-    const double x2 = mks_x2(g.hslope, y[2], *x2w);
-    *x2w = x2;
+    const double x2 = mks_x2(g.hslope, y[2], x2_start(g, y[2]));
     double f1 = (x1 - g.lnr_in) * g.inv_d1 - 0.5;
     double f2 = x2 * g.n2 - 0.5;
     f1 = ::fmin(::fmax(f1, 0.0), (double)(g.n1 - 1));
@@ -139,22 +172,19 @@ __device__ inline bool sample_fluid(const DevGrid& g, int slow_light, int fast_s
 #pragma unroll
         for (int f = 0; f < 4; ++f) out[f] = v0[f];
     }
-    return true;
 }
 
 // Fluid frame of a circular flow u = u^t (1, 0, 0, Omega) in the KS metric, with the ZAMO
 // angular velocity where Omega is not timelike.  Returns nu_r = -k.u and the cosine of the
 // fluid-frame angle between k and the unit toroidal field b ~ (u_phi, 0, 0, -u_t).
 template <class T>
-__host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T omega, T* nu_r, T* cos_b)
+__host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T s, T c, T omega, T* nu_r, T* cos_b)
 {
     using namespace rt;
     const T r = y[1];
-    T s, c;
-    sincos_(y[2], &s, &c);
     const T s2 = s * s;
     const T sig = r * r + a2 * c * c;
-    const T z = T(2.0) * M * r * rcp(sig);
+    const T z = T(2.0) * M * r * rcp_nr(sig);
     const T z1 = T(1.0) + z;
     const T gtt = z - T(1.0);
     const T gtp = -a * z * s2;
@@ -167,7 +197,7 @@ __host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T omega,
         D = -(gtt + T(2.0) * gtp * omega + gpp * omega * omega);
         zamo = true;
     }
-    const T ut = rcp(sqrt_(D));
+    const T ut = rsqrt_nr(D);
     const T up = omega * ut;
     const T u_t = gtt * ut + gtp * up;
     const T u_p = gtp * ut + gpp * up;
@@ -176,8 +206,8 @@ __host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T omega,
     const T k_p = gtp * kt + grp * kr + gpp * kp;
     const T nr = -(k_t * ut + k_p * up);
     const T bb = gtt * u_p * u_p - T(2.0) * gtp * u_p * u_t + gpp * u_t * u_t;
-    const T kb = (k_t * u_p - k_p * u_t) * rcp(sqrt_(bb));
-    T cb = kb / nr;
+    const T kb = (k_t * u_p - k_p * u_t) * rsqrt_nr(bb);
+    T cb = kb * rcp_nr(nr);
     cb = fmin_(fmax_(cb, T(-1.0)), T(1.0));
     *nu_r = nr;
     *cos_b = cb;
@@ -216,6 +246,18 @@ __host__ __device__ inline void closure_exact(T nu, T ne, T the, T bf, T sinb, T
     *j = jv;
     *alpha = jv / B;
     *bnu = B;
+}
+
+// Contribution of one step to the observed intensity before attenuation by the optical depth
+// already between the point and the camera, A = S (1 - exp(-dtau)) / nu_r^3 (j ds / nu_r^3
+// when dtau = 0), and the step's optical depth dtau = alpha ds (Sec. 3.1, per-step formal
+// solution in the backward scheme).
+template <class T>
+__host__ __device__ inline void step_source(T j, T al, T S, T ds, T inr3, T& A, T& dtau)
+{
+    using namespace rt;
+    dtau = al * ds;
+    A = (dtau > T(0.0)) ? S * (-expm1_(-dtau)) * inr3 : j * ds * inr3;
 }
 
 // Backward formal-solution update of one frequency (Sec. 3.1): the step's emission with

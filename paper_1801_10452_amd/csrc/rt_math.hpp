@@ -41,6 +41,60 @@ __host__ __device__ inline void sincospi_(double x, double* s, double* c)
 __host__ __device__ inline bool finite_(double x) { return ::isfinite(x); }
 __host__ __device__ inline double val(double x) { return x; }
 
+// sin and cos for moderate arguments (|x| < 1e3 keeps the reduction exact): x = k pi/2 + r with
+// k = rint(2x/pi) and r from a three-term Cody-Waite subtraction (pi/2 split into a 40-bit head,
+// so k times the head is exact, and two tails), then Taylor polynomials of sin r through r^17
+// and cos r through r^18 on |r| <= pi/4 (truncation below 1e-19) and the quadrant identities.
+__host__ __device__ inline void sincos_small(double x, double* s, double* c)
+{
+    const double k = __builtin_rint(x * 0.6366197723675814);
+    double r = __builtin_fma(-k, 1.5707963267941523, x);
+    r = __builtin_fma(-k, 7.443547480486623e-13, r);
+    r = __builtin_fma(-k, -1.2536990206932499e-29, r);
+    const double r2 = r * r;
+    const double ps = -1.0 / 6.0 + r2 * (1.0 / 120.0 + r2 * (-1.0 / 5040.0 + r2 * (1.0 / 362880.0 + r2 * (-1.0 / 39916800.0
+                    + r2 * (1.0 / 6227020800.0 + r2 * (-1.0 / 1307674368000.0 + r2 * (1.0 / 355687428096000.0)))))));
+    const double pc = -0.5 + r2 * (1.0 / 24.0 + r2 * (-1.0 / 720.0 + r2 * (1.0 / 40320.0 + r2 * (-1.0 / 3628800.0
+                    + r2 * (1.0 / 479001600.0 + r2 * (-1.0 / 87178291200.0 + r2 * (1.0 / 20922789888000.0
+                    + r2 * (-1.0 / 6402373705728000.0))))))));
+    const double sn = r + r * r2 * ps;
+    const double cs = 1.0 + r2 * pc;
+    const int q = (int)k & 3;
+    const double a = (q & 1) ? cs : sn;   // |sin x|
+    const double b = (q & 1) ? sn : cs;   // |cos x|
+    *s = (q & 2) ? -a : a;
+    *c = ((q + 1) & 2) ? -b : b;
+}
+
+// Reciprocal without the IEEE division sequence: the hardware estimate (about 2^-26 relative
+// error) refined by two Newton-Raphson steps r <- r (2 - x r), which square the error each
+// time (full double precision; not correctly rounded in every case).
+__host__ __device__ inline double rcp_nr(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+// 1/sqrt(x): hardware estimate refined by two Newton-Raphson steps r <- r (3 - x r^2) / 2.
+__host__ __device__ inline double rsqrt_nr(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    r = r * __builtin_fma(-h * r, r, 1.5);
+    return r * __builtin_fma(-h * r, r, 1.5);
+#else
+    return 1.0 / std::sqrt(x);
+#endif
+}
+
 // ---------------------------------------------------------------- operation counting (host only)
 struct OpTally {
     double flops = 0.0, special = 0.0;
@@ -64,6 +118,8 @@ inline bool operator>(OpCounted a, OpCounted b) { return a.v > b.v; }
 inline bool operator<=(OpCounted a, OpCounted b) { return a.v <= b.v; }
 inline bool operator>=(OpCounted a, OpCounted b) { return a.v >= b.v; }
 inline OpCounted rcp(OpCounted x) { g_tally.special += 1; return 1.0 / x.v; }
+inline OpCounted rcp_nr(OpCounted x) { g_tally.special += 1; return 1.0 / x.v; }
+inline OpCounted rsqrt_nr(OpCounted x) { g_tally.special += 1; return 1.0 / std::sqrt(x.v); }
 inline OpCounted sqrt_(OpCounted x) { g_tally.special += 1; return std::sqrt(x.v); }
 inline OpCounted cbrt_(OpCounted x) { g_tally.special += 1; return std::cbrt(x.v); }
 inline OpCounted exp_(OpCounted x) { g_tally.special += 1; return std::exp(x.v); }
@@ -78,6 +134,7 @@ inline void sincos_(OpCounted x, OpCounted* s, OpCounted* c)
     *s = std::sin(x.v);
     *c = std::cos(x.v);
 }
+inline void sincos_small(OpCounted x, OpCounted* s, OpCounted* c) { sincos_(x, s, c); }
 inline void sincospi_(OpCounted x, OpCounted* s, OpCounted* c)
 {
     g_tally.special += 1;

@@ -32,13 +32,6 @@ __device__ inline unsigned lane_rank(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-__device__ inline unsigned long long wave_sum(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // Transfer arithmetic in precision TT (double or float); the closure inputs come in FP64.
 template <class TT>
 struct Transfer;
@@ -53,7 +46,7 @@ struct Transfer<double> {
         ne = fl[0]; the = fl[1]; bf = fl[2];
         nr = nr_;
         ds = dsv;
-        inr3 = 1.0 / (nr * nr * nr);
+        inr3 = rt::rcp_nr(nr * nr * nr);
         const double s2 = 1.0 - cosb * cosb;
         sinb = s2 > 0.0 ? ::sqrt(s2) : 0.0;
         emits = (ne > 0.0 && the > 0.0 && bf > 0.0 && sinb > 0.0);
@@ -61,7 +54,7 @@ struct Transfer<double> {
         if (emits && p.closure != CL_CONST)
             k2_inv = (p.closure == CL_K2_PAPER) ? 1.0 / (2.0 * the * the) : ::exp(-pl::ln_k2(p.k2, ::log(the)));
     }
-    __device__ inline void update(const TraceParams& p, double nu_obs, double& I, double& tau) const
+    __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
         double j, al, S;
         if (p.closure == CL_CONST) {
@@ -73,7 +66,7 @@ struct Transfer<double> {
         } else {
             return;
         }
-        pl::transfer_update(j, al, S, ds, inr3, I, tau);
+        pl::step_source(j, al, S, ds, inr3, A, dtau);
     }
 };
 
@@ -96,9 +89,9 @@ struct Transfer<float> {
         k2_inv = 0.0f;
         if (emits && p.closure != CL_CONST)
             k2_inv = (p.closure == CL_K2_PAPER) ? 1.0f / (2.0f * the * the)
-                                               : ::expf(-(float)pl::ln_k2(p.k2, ::log(fl[1])));
+                                               : ::expf(-pl::ln_k2f(p.k2, ::logf(the)));
     }
-    __device__ inline void update(const TraceParams& p, double nu_obs, float& I, float& tau) const
+    __device__ inline void contribution(const TraceParams& p, double nu_obs, float& A, float& dtau) const
     {
         float j, al, S;
         if (p.closure == CL_CONST) {
@@ -117,19 +110,86 @@ struct Transfer<float> {
         } else {
             return;
         }
-        pl::transfer_update(j, al, S, ds, inr3, I, tau);
+        pl::step_source(j, al, S, ds, inr3, A, dtau);
     }
 };
 
+// ---------------------------------------------------------------------------------------
+// Sample compaction.  A lane whose ray takes a step inside the plasma does not evaluate the
+// sample at once: it queues the point (ten doubles) in its wave's LDS area, up to QK per lane.
+// When some lane's queue is full, or a ray with queued samples terminates, the wave evaluates
+// all queued samples together -- sample i of the flattened queue on lane i mod 64 -- so the
+// expensive part (MKS map, gather, fluid frame, closure) runs on full waves.  Each owner then
+// folds its own results into (I, tau) in the order the samples were taken, which keeps the
+// backward transfer identical to evaluating every sample right after its step.
+// ---------------------------------------------------------------------------------------
+constexpr int N_FIELDS = 10;   // t, r, theta, phi, k^t, k^r, k^phi, |dlambda|, sin, cos
+
+struct LaneInfo {
+    double a;
+    int grid, fast_snap, nu_base, n_nu;
+};
+
 template <int NNU, class TT>
-__global__ void __launch_bounds__(256) trace_kernel(TraceParams p)
+struct Queue {
+    // pending samples per lane: two while the LDS area stays within 32 KiB per wave
+    static constexpr int K = (64 * 2 * (N_FIELDS * 8 + 2 * NNU * (int)sizeof(TT) + 4) <= 32768) ? 2 : 1;
+    static constexpr int SLOTS = 64 * K;
+    static constexpr size_t FIELD_BYTES = (size_t)N_FIELDS * SLOTS * sizeof(double);
+    static constexpr size_t RES_BYTES = (size_t)2 * NNU * SLOTS * sizeof(TT);
+    static constexpr size_t MAP_BYTES = (size_t)SLOTS * sizeof(int);
+    static constexpr size_t INFO_BYTES = 64 * sizeof(LaneInfo);
+    static constexpr size_t PER_WAVE = (FIELD_BYTES + RES_BYTES + MAP_BYTES + INFO_BYTES + 15) / 16 * 16;
+};
+
+__device__ inline void wave_lds_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Evaluate one queued sample: fluid state, fluid frame, closure, and per frequency the
+// attenuation-free contribution A (observed units) and the optical depth dtau of the step.
+template <int NNU, class TT>
+__device__ inline bool eval_sample(const TraceParams& p, const double* q, const LaneInfo& li, TT* A, TT* dtau)
+{
+    const DevGrid& G = p.grids[li.grid];
+    const double y[8] = {q[0], q[1], q[2], q[3], q[4], q[5], 0.0, q[6]};
+    double fl[4];
+    pl::sample_fluid(G, p.slow_light, li.fast_snap, y, fl);
+    double nr, cb;
+    const bool zamo = pl::fluid_frame(li.a, li.a * li.a, p.M, y, q[8], q[9], fl[3], &nr, &cb);
+    Transfer<TT> tr;
+    tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+#pragma unroll
+    for (int f = 0; f < NNU; ++f) {
+        A[f] = TT(0);
+        dtau[f] = TT(0);
+        if (f < li.n_nu) tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
+    }
+    return zamo;
+}
+
+template <int NNU, class TT, int WPE>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(WPE, 8)))
+trace_kernel(TraceParams p)
+{
+    using Q = Queue<NNU, TT>;
+    constexpr int K = Q::K;
+    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
+    unsigned char* wbase = smem + (size_t)(threadIdx.x >> 6) * Q::PER_WAVE;
+    double* fields = reinterpret_cast<double*>(wbase);                                  // [N_FIELDS][SLOTS]
+    TT* res = reinterpret_cast<TT*>(wbase + Q::FIELD_BYTES);                            // [SLOTS][2*NNU]
+    int* slot_map = reinterpret_cast<int*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES);      // [SLOTS]
+    LaneInfo* info = reinterpret_cast<LaneInfo*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES + Q::MAP_BYTES);
     const double M = p.M;
 
+    // ray state of this lane
     double y[8];
-    double a = 0.0, r_stop = 0.0, r_esc = 0.0, x2w = 0.5;
-    int job = 0, steps = 0, pix = 0, n_nu = 0, nu_base = 0, grid = 0, fast_snap = 0;
+    double a = 0.0, r_stop = 0.0, r_esc = 0.0, sth = 0.0, cth = 1.0;
+    int job = 0, steps = 0, pix = 0, n_nu = 0, grid = 0, pending = 0;
     bool active = false;
     TT I[NNU], tau[NNU];
 #pragma unroll
@@ -137,6 +197,7 @@ __global__ void __launch_bounds__(256) trace_kernel(TraceParams p)
 #pragma unroll
     for (int i = 0; i < 8; ++i) y[i] = 0.0;
 
+    // wave-level statistics (ballot counts: scalar registers)
     unsigned long long c_rays = 0, c_steps = 0, c_samples = 0, c_hor = 0, c_esc = 0, c_max = 0, c_pole = 0,
                        c_num = 0, c_zamo = 0;
 
@@ -153,7 +214,7 @@ __global__ void __launch_bounds__(256) trace_kernel(TraceParams p)
                     if (drained) break;
                     unsigned t = 0;
                     if (lane == 0) t = atomicAdd(p.tile_counter, 1u);
-                    t = __shfl(t, 0, 64);
+                    t = __builtin_amdgcn_readfirstlane(t);
                     if ((long long)t >= p.n_tiles) {
                         drained = true;
                         break;
@@ -170,22 +231,22 @@ __global__ void __launch_bounds__(256) trace_kernel(TraceParams p)
                     job = find_job(p.jobs, p.n_jobs, tile);
                     const DevJob& J = p.jobs[job];
                     const long long lt = tile - J.tile_base;
-                    const int px = (int)(lt % J.tiles_x) * 8 + (slot & 7);
-                    const int py = (int)(lt / J.tiles_x) * 8 + (slot >> 3);
+                    const int tw = 1 << p.tile_shift;
+                    const int px = (int)(lt % J.tiles_x) * tw + (slot & (tw - 1));
+                    const int py = (int)(lt / J.tiles_x) * (64 >> p.tile_shift) + (slot >> p.tile_shift);
                     if (px < J.nx && py < J.ny) {
                         const double alpha = -J.fov + (px + 0.5) * J.dalpha;
                         const double beta = -J.fov + (py + 0.5) * J.dbeta;
                         a = J.a;
                         const rk::Spin<double> sp = rk::make_spin(a, M);
                         rk::camera_ray(sp, J.r_cam, J.incl, J.sin_i, J.cos_i, alpha, beta, J.t_init, y);
+                        rt::sincos_small(y[2], &sth, &cth);
                         r_stop = J.r_stop;
                         r_esc = J.r_cam;
-                        x2w = y[2] * M_1_PI;
                         pix = py * J.nx + px;
                         n_nu = J.n_nu;
-                        nu_base = J.nu_base;
                         grid = J.grid;
-                        fast_snap = J.fast_snap;
+                        info[lane] = LaneInfo{a, J.grid, J.fast_snap, J.nu_base, J.n_nu};
                         steps = 0;
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) { I[f] = TT(0); tau[f] = TT(0); }
@@ -197,22 +258,26 @@ __global__ void __launch_bounds__(256) trace_kernel(TraceParams p)
                 n_idle = __popcll(idle);
             }
         }
-        if (__ballot(active) == 0ull) break;   // every lane idle: the queue is drained
+        const unsigned long long act = __ballot(active);
+        if (act == 0ull) break;   // every lane idle (queues are empty): the tile queue is drained
+        c_steps += __popcll(act);
 
         // ------------------------------------------------------------ one step of every active ray
+        bool reflected = false;
+        int status = RAY_RUNNING;
         if (active) {
             const rk::Spin<double> sp = rk::make_spin(a, M);
             const double dl = -rk::step_size(p.eps, y);
-            rk::rk4_step(sp, y, dl);
+            rk::rk4_step(sp, y, dl, sth, cth);
             ++steps;
-            int status = RAY_RUNNING;
             bool fin = true;
 #pragma unroll
             for (int i = 0; i < 8; ++i) fin = fin && ::isfinite(y[i]);
             if (!fin) {
                 status = RAY_NUMERIC;
             } else {
-                c_pole += rk::reflect_pole(y);
+                reflected = rk::reflect_pole(y);
+                rt::sincos_small(y[2], &sth, &cth);
                 if (y[1] < r_stop)
                     status = RAY_HORIZON;
                 else if (y[1] > r_esc)
@@ -220,47 +285,105 @@ __global__ void __launch_bounds__(256) trace_kernel(TraceParams p)
                 else if (steps >= p.max_steps)
                     status = RAY_MAXSTEP;
             }
-            if (status == RAY_RUNNING) {
-                const DevGrid& G = p.grids[grid];
-                double fl[4];
-                if (pl::sample_fluid(G, p.slow_light, fast_snap, y, &x2w, fl)) {
-                    ++c_samples;
-                    double nr, cb;
-                    c_zamo += pl::fluid_frame(a, a * a, M, y, fl[3], &nr, &cb);
-                    Transfer<TT> tr;
-                    tr.setup(p, fl, nr, cb, nr * ::fabs(dl) * p.length_unit);
-#pragma unroll
-                    for (int f = 0; f < NNU; ++f)
-                        if (f < n_nu) tr.update(p, p.nu[nu_base + f], I[f], tau[f]);
-                }
-            } else {
-                const DevJob& J = p.jobs[job];
-                const long long npix = (long long)J.nx * J.ny;
-                double* o = p.out + J.out_base + pix;
-#pragma unroll
-                for (int f = 0; f < NNU; ++f)
-                    if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : (double)I[f];
-                if (p.ray_status) p.ray_status[J.pix_base + pix] = status;
-                if (p.ray_steps) p.ray_steps[J.pix_base + pix] = steps;
-                c_rays += 1;
-                c_steps += steps;
-                c_hor += status == RAY_HORIZON;
-                c_esc += status == RAY_ESCAPED;
-                c_max += status == RAY_MAXSTEP;
-                c_num += status == RAY_NUMERIC;
-                active = false;
+            if (status == RAY_RUNNING && pl::in_plasma(p.grids[grid], y[1])) {
+                // queue the sample point
+                const int s = lane * K + pending;
+                fields[0 * Q::SLOTS + s] = y[0];
+                fields[1 * Q::SLOTS + s] = y[1];
+                fields[2 * Q::SLOTS + s] = y[2];
+                fields[3 * Q::SLOTS + s] = y[3];
+                fields[4 * Q::SLOTS + s] = y[4];
+                fields[5 * Q::SLOTS + s] = y[5];
+                fields[6 * Q::SLOTS + s] = y[7];
+                fields[7 * Q::SLOTS + s] = -dl;
+                fields[8 * Q::SLOTS + s] = sth;
+                fields[9 * Q::SLOTS + s] = cth;
+                ++pending;
             }
+        }
+        c_pole += __popcll(__ballot(reflected));
+
+        // ------------------------------------------------------------ evaluate queued samples
+        const bool must_flush = (pending == K) || (status != RAY_RUNNING && pending > 0);
+        if (__ballot(must_flush)) {
+            // flattened queue: lane L's samples follow those of the lanes below it
+            unsigned base_rank = 0, total = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const unsigned long long b = __ballot(pending > k);
+                base_rank += lane_rank(b);
+                total += __popcll(b);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < pending) slot_map[base_rank + k] = lane * K + k;
+            wave_lds_sync();
+            for (unsigned r0 = 0; r0 < total; r0 += 64) {
+                const unsigned i = r0 + lane;
+                bool zamo = false;
+                if (i < total) {
+                    const int s = slot_map[i];
+                    double q[N_FIELDS];
+#pragma unroll
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                    TT A[NNU], dt[NNU];
+                    zamo = eval_sample<NNU, TT>(p, q, info[s / K], A, dt);
+#pragma unroll
+                    for (int f = 0; f < NNU; ++f) {
+                        res[s * 2 * NNU + f] = A[f];
+                        res[s * 2 * NNU + NNU + f] = dt[f];
+                    }
+                }
+                c_zamo += __popcll(__ballot(zamo));
+            }
+            c_samples += total;
+            wave_lds_sync();
+            // each owner folds its samples in order: I += exp(-tau) A, tau += dtau
+            for (int k = 0; k < K; ++k) {
+                if (k < pending) {
+                    const int s = lane * K + k;
+#pragma unroll
+                    for (int f = 0; f < NNU; ++f) {
+                        if (f < n_nu) {
+                            I[f] = I[f] + rt::exp_(-tau[f]) * res[s * 2 * NNU + f];
+                            tau[f] = tau[f] + res[s * 2 * NNU + NNU + f];
+                        }
+                    }
+                }
+            }
+            pending = 0;
+            wave_lds_sync();
+        }
+
+        // ------------------------------------------------------------ finished rays
+        if (status != RAY_RUNNING) {
+            const DevJob& J = p.jobs[job];
+            const long long npix = (long long)J.nx * J.ny;
+            double* o = p.out + J.out_base + pix;
+#pragma unroll
+            for (int f = 0; f < NNU; ++f)
+                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : (double)I[f];
+            if (p.ray_status) p.ray_status[J.pix_base + pix] = status;
+            if (p.ray_steps) p.ray_steps[J.pix_base + pix] = steps;
+            active = false;
+        }
+        const unsigned long long done = __ballot(status != RAY_RUNNING);
+        if (done) {
+            c_rays += __popcll(done);
+            c_hor += __popcll(__ballot(status == RAY_HORIZON));
+            c_esc += __popcll(__ballot(status == RAY_ESCAPED));
+            c_max += __popcll(__ballot(status == RAY_MAXSTEP));
+            c_num += __popcll(__ballot(status == RAY_NUMERIC));
         }
     }
 
     // ------------------------------------------------------------ statistics, one atomic per counter per wave
-    const unsigned long long s[ST_COUNT] = {wave_sum(c_rays), wave_sum(c_steps), wave_sum(c_samples), wave_sum(c_hor),
-                                            wave_sum(c_esc), wave_sum(c_max), wave_sum(c_pole), wave_sum(c_num),
-                                            0ull, wave_sum(c_zamo)};
     if (lane == 0) {
+        const unsigned long long st[ST_COUNT] = {c_rays, c_steps, c_samples, c_hor, c_esc, c_max, c_pole, c_num,
+                                                 0ull, c_zamo};
 #pragma unroll
         for (int i = 0; i < ST_COUNT; ++i)
-            if (s[i]) atomicAdd(p.stats + i, s[i]);
+            if (st[i]) atomicAdd(p.stats + i, st[i]);
     }
 }
 
@@ -296,20 +419,20 @@ __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* sta
 }
 
 template <int NNU, class TT>
-hipError_t launch_nnu(const TraceParams& p, int blocks, int threads, hipStream_t st)
+const void* symbol_of(int wpe)
 {
-    hipLaunchKernelGGL((trace_kernel<NNU, TT>), dim3(blocks), dim3(threads), 0, st, p);
-    return hipGetLastError();
+    return wpe >= 3 ? (const void*)trace_kernel<NNU, TT, 3>
+         : wpe == 2 ? (const void*)trace_kernel<NNU, TT, 2> : (const void*)trace_kernel<NNU, TT, 1>;
 }
 
 template <class TT>
-hipError_t launch_tt(const TraceParams& p, int max_nu, int blocks, int threads, hipStream_t st)
+const void* symbol_tt(int max_nu, int wpe)
 {
-    if (max_nu <= 1) return launch_nnu<1, TT>(p, blocks, threads, st);
-    if (max_nu <= 4) return launch_nnu<4, TT>(p, blocks, threads, st);
-    if (max_nu <= 8) return launch_nnu<8, TT>(p, blocks, threads, st);
-    if (max_nu <= 16) return launch_nnu<16, TT>(p, blocks, threads, st);
-    return launch_nnu<32, TT>(p, blocks, threads, st);
+    if (max_nu <= 1) return symbol_of<1, TT>(wpe);
+    if (max_nu <= 4) return symbol_of<4, TT>(wpe);
+    if (max_nu <= 8) return symbol_of<8, TT>(wpe);
+    if (max_nu <= 16) return symbol_of<16, TT>(wpe);
+    return symbol_of<32, TT>(wpe);
 }
 
 }  // namespace
@@ -320,9 +443,11 @@ hipError_t launch_reset(unsigned int* tile_counter, unsigned long long* stats, h
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int blocks, int threads, hipStream_t st)
+hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, int blocks, int threads, hipStream_t st)
 {
-    return fp32 ? launch_tt<float>(p, max_nu, blocks, threads, st) : launch_tt<double>(p, max_nu, blocks, threads, st);
+    const void* fn = trace_kernel_symbol(max_nu, fp32, wpe);
+    void* args[] = {const_cast<TraceParams*>(&p)};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, trace_kernel_lds(max_nu, fp32, threads), st);
 }
 
 hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* flux,
@@ -332,21 +457,29 @@ hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const 
     return hipGetLastError();
 }
 
-const void* trace_kernel_symbol(int max_nu, bool fp32)
+size_t trace_kernel_lds(int max_nu, bool fp32, int threads)
 {
-    if (fp32)
-        return max_nu <= 1 ? (const void*)trace_kernel<1, float> : max_nu <= 4 ? (const void*)trace_kernel<4, float>
-             : max_nu <= 8 ? (const void*)trace_kernel<8, float> : max_nu <= 16 ? (const void*)trace_kernel<16, float>
-             : (const void*)trace_kernel<32, float>;
-    return max_nu <= 1 ? (const void*)trace_kernel<1, double> : max_nu <= 4 ? (const void*)trace_kernel<4, double>
-         : max_nu <= 8 ? (const void*)trace_kernel<8, double> : max_nu <= 16 ? (const void*)trace_kernel<16, double>
-         : (const void*)trace_kernel<32, double>;
+    const int waves = threads / 64;
+    auto per = [&](auto tt) -> size_t {
+        using TT = decltype(tt);
+        if (max_nu <= 1) return Queue<1, TT>::PER_WAVE;
+        if (max_nu <= 4) return Queue<4, TT>::PER_WAVE;
+        if (max_nu <= 8) return Queue<8, TT>::PER_WAVE;
+        if (max_nu <= 16) return Queue<16, TT>::PER_WAVE;
+        return Queue<32, TT>::PER_WAVE;
+    };
+    return waves * (fp32 ? per(0.0f) : per(0.0));
 }
 
-hipError_t trace_kernel_attributes(int max_nu, bool fp32, int* vgprs, int* spill_bytes, int* max_threads)
+const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe)
+{
+    return fp32 ? symbol_tt<float>(max_nu, wpe) : symbol_tt<double>(max_nu, wpe);
+}
+
+hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, int* vgprs, int* spill_bytes, int* max_threads)
 {
     hipFuncAttributes at;
-    const hipError_t e = hipFuncGetAttributes(&at, trace_kernel_symbol(max_nu, fp32));
+    const hipError_t e = hipFuncGetAttributes(&at, trace_kernel_symbol(max_nu, fp32, wpe));
     if (e != hipSuccess) return e;
     if (vgprs) *vgprs = at.numRegs;
     if (spill_bytes) *spill_bytes = (int)at.localSizeBytes;

@@ -60,10 +60,19 @@ class CStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CPlan(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_threshold", C.c_int32),
+                ("tile_width", C.c_int32), ("min_waves_per_simd", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # every symbol include/raptor.h declares
 EXPORTS = ["raptor_create", "raptor_destroy", "raptor_last_error", "raptor_grid_upload", "raptor_grid_release",
            "raptor_default_opts", "raptor_trace_image", "raptor_trace_spectrum", "raptor_trace_spectrum_ex",
-           "raptor_trace_batch", "raptor_work_per_unit"]
+           "raptor_trace_batch", "raptor_work_per_unit", "raptor_get_plan", "raptor_set_plan",
+           "raptor_autotune_batch", "raptor_kernel_info"]
 
 _lib = None
 
@@ -102,6 +111,11 @@ def lib():
         L.raptor_trace_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
                                          C.c_int32, V, V, C.POINTER(CStats)]
         L.raptor_work_per_unit.argtypes = [DP] * 6
+        L.raptor_get_plan.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan)]
+        L.raptor_set_plan.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan)]
+        L.raptor_autotune_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
+                                            C.c_int32, C.c_int32, C.POINTER(CPlan), DP]
+        L.raptor_kernel_info.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan), IP, IP, IP]
         for name in EXPORTS:
             if name not in ("raptor_destroy", "raptor_last_error", "raptor_grid_release"):
                 getattr(L, name).restype = C.c_int
@@ -241,6 +255,48 @@ class Context:
         self._check(lib().raptor_trace_batch(self.h, carr, n, garr, C.byref(opts), nu.ctypes.data_as(DP), n_nu,
                                              _ptr(images), _ptr(flux), C.byref(st)))
         return images, flux, st
+
+
+def make_plan(threads=256, blocks_per_cu=0, refill_threshold=1, tile_width=8, min_waves_per_simd=2) -> CPlan:
+    return CPlan(threads, blocks_per_cu, refill_threshold, tile_width, min_waves_per_simd, (C.c_int32 * 3)())
+
+
+def _batch_args(cams, grids, nu):
+    n = len(cams)
+    nu = np.asarray(nu, dtype=np.float64)
+    if nu.ndim == 1:
+        nu = np.tile(nu, (n, 1))
+    nu = np.ascontiguousarray(nu)
+    carr = (CCamera * n)(*[make_camera(c) for c in cams])
+    garr = (C.c_void_p * n)(*[g.ptr for g in grids])
+    return n, nu, carr, garr
+
+
+def get_plan(ctx, n_nu, prec):
+    pl = CPlan()
+    ctx._check(lib().raptor_get_plan(ctx.h, n_nu, prec, C.byref(pl)))
+    return pl
+
+
+def set_plan(ctx, n_nu, prec, plan):
+    ctx._check(lib().raptor_set_plan(ctx.h, n_nu, prec, C.byref(plan)))
+
+
+def autotune_batch(ctx, cams, grids, nu, opts=None, reps=2):
+    """Run the library's autotuner on this batch; returns (best plan, best kernel ms)."""
+    opts = opts or default_opts()
+    n, nu, carr, garr = _batch_args(cams, grids, nu)
+    best = CPlan()
+    ms = C.c_double()
+    ctx._check(lib().raptor_autotune_batch(ctx.h, carr, n, garr, C.byref(opts), nu.ctypes.data_as(DP), nu.shape[1],
+                                           reps, C.byref(best), C.byref(ms)))
+    return best, ms.value
+
+
+def kernel_info(ctx, n_nu, prec, plan):
+    v = [C.c_int32() for _ in range(3)]
+    ctx._check(lib().raptor_kernel_info(ctx.h, n_nu, prec, C.byref(plan), *[C.byref(x) for x in v]))
+    return {"vgprs": v[0].value, "scratch_bytes": v[1].value, "blocks_per_cu": v[2].value}
 
 
 def split_batch_images(images, cams, n_nu):
