@@ -51,9 +51,10 @@ enum { RAPTOR_MEM_HOST = 0, RAPTOR_MEM_DEVICE = 1 };
 /* Emission / absorption closure.  EXACT: the Leung et al. fit with the exact Bessel K2 and
  * Kirchhoff absorption (Sec. 4.2.2).  K2_PAPER: same with the paper's K2 ~ 2 Theta_e^2.
  * CONST: j = const_j, alpha = const_alpha wherever the grid has plasma (test closure).
- * MLP: the learned surrogate (see raptor_mlp_*) inside its training box, EXACT outside. */
+ * MLP / MLP_BF16: the learned surrogate (see raptor_mlp_*) in its split-BF16 or plain-BF16
+ * form inside its training box, EXACT outside; needs parameters loaded in the context. */
 enum { RAPTOR_CLOSURE_EXACT = 0, RAPTOR_CLOSURE_K2_PAPER = 1, RAPTOR_CLOSURE_CONST = 2,
-       RAPTOR_CLOSURE_MLP = 3 };
+       RAPTOR_CLOSURE_MLP = 3, RAPTOR_CLOSURE_MLP_BF16 = 4 };
 /* Ray termination codes written by raptor_trace_spectrum_ex. */
 enum { RAPTOR_RAY_HORIZON = 1, RAPTOR_RAY_ESCAPED = 2, RAPTOR_RAY_MAXSTEP = 3,
        RAPTOR_RAY_NUMERIC = 4 };
@@ -115,7 +116,8 @@ typedef struct {
 } raptor_opts;
 
 /* Counters of the last trace call.  ray_steps counts accepted RK4 steps, samples the steps
- * at which the plasma was sampled. */
+ * at which the plasma was sampled, n_mlp_fallback the sample-frequencies that the learned
+ * closure handed to the exact closure (inputs outside its box). */
 typedef struct {
     uint64_t rays, ray_steps, samples, n_horizon, n_escaped, n_maxstep, n_pole, n_numeric,
              n_mlp_fallback, n_zamo_fallback;
@@ -182,6 +184,69 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
                                     const raptor_grid* const* grids, const raptor_opts* opts,
                                     const double* nu_hz, int32_t n_nu, int32_t reps, raptor_plan* best,
                                     double* best_ms);
+
+/* ------------------------------------------------------------------------------------------
+ * Learned closure (an addition to the paper's method).  A 3 -> 64 -> 64 -> 64 -> 64 -> 2 SiLU
+ * network maps (ln(nu/nu_c), ln Theta_e, cos theta_B), normalised to [-1, 1] over the box
+ * nu/nu_c in [1e-2, 1e6], Theta_e in [0.1, 100], |cos theta_B| <= 0.999, to standardised
+ * ln j_hat = ln(j / (n_e nu_c J0)) and ln alpha_hat = ln j_hat - 2 ln(nu/nu_c) - ln Theta_e,
+ * J0 = sqrt2 pi e^2 / (3c), where alpha_hat is the Rayleigh-Jeans absorption in units of
+ * n_e J0 / (2 m_e nu_c); the exact Planck factor is applied when the network is used
+ * (closure RAPTOR_CLOSURE_MLP), and the exact closure of Sec. 4.2.2 is used outside the box.
+ * Training samples are the exact closure, evaluated on the device.  Parameters: for each
+ * layer W[out][in] then b[out], 12866 floats.
+ * ------------------------------------------------------------------------------------------ */
+enum { RAPTOR_MLP_SPLIT = 0,   /* BF16 matrix cores, operands split into BF16 hi + lo pairs */
+       RAPTOR_MLP_BF16 = 1,    /* BF16 matrix cores, BF16 operands */
+       RAPTOR_MLP_F32 = 2 };   /* FP32 vector arithmetic (reference form) */
+enum { RAPTOR_MLP_PARAMS = 12866 };
+
+typedef struct {
+    int64_t n_train;             /* training samples generated on the device (default 1e7) */
+    int64_t n_val;               /* validation samples (default 1e5) */
+    int32_t epochs;              /* passes over the training samples (default 6) */
+    int32_t batch;               /* samples per Adam step, a multiple of 64 (default 4096) */
+    float lr, lr_final;          /* Adam step size, cosine-decayed from lr to lr_final */
+    float beta1, beta2, adam_eps, weight_decay;
+    uint64_t train_seed, val_seed;
+    int32_t form;                /* forward form used in training and validation: SPLIT or BF16 */
+    int32_t reserved;
+} raptor_mlp_train_cfg;
+
+typedef struct {
+    int64_t steps;
+    double train_loss;           /* mean squared error (standardised) over the last epoch */
+    double val_rms[2];           /* validation rms error of ln j_hat and ln alpha_hat */
+    double val_max[2];           /* validation max |error| */
+    double val_rms_bright;       /* rms error of ln j_hat where ln j_hat > -20 */
+    double train_ms;             /* wall time of the training loop */
+} raptor_mlp_report;
+
+/* Defaults of the training configuration (seeds of the synthetic workload included). */
+raptor_status raptor_mlp_default_cfg(raptor_mlp_train_cfg* cfg);
+/* Random initial parameters, U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a SplitMix64 stream. */
+raptor_status raptor_mlp_init(raptor_ctx* ctx, uint64_t seed);
+/* Train on the device: sample generation, forward and backward passes on the matrix cores,
+ * Adam with FP32 parameters.  Requires initialised parameters (raptor_mlp_init or set). */
+raptor_status raptor_mlp_train(raptor_ctx* ctx, const raptor_mlp_train_cfg* cfg, raptor_mlp_report* report);
+/* Parameters as 12866 floats (host memory). */
+raptor_status raptor_mlp_get_params(raptor_ctx* ctx, float* params, int32_t n);
+raptor_status raptor_mlp_set_params(raptor_ctx* ctx, const float* params, int32_t n);
+/* Checkpoint: a versioned blob holding the parameters, the Adam moments and step count.
+ * get: *n in = capacity (blob may be NULL to query), *n out = size. */
+raptor_status raptor_mlp_get_weights(raptor_ctx* ctx, void* blob, size_t* n);
+raptor_status raptor_mlp_set_weights(raptor_ctx* ctx, const void* blob, size_t n);
+/* y[n][2] = network(x[n][3]) for normalised inputs, in the given form (host buffers). */
+raptor_status raptor_mlp_forward(raptor_ctx* ctx, int32_t form, const float* x, int64_t n, float* y);
+/* dparams[12866] = gradient of sum_i dy[i] . y[i] with respect to the parameters; form BF16
+ * (the training backward pass) or F32. */
+raptor_status raptor_mlp_backward(raptor_ctx* ctx, int32_t form, const float* x, const float* dy, int64_t n,
+                                  float* dparams);
+/* For raw closure inputs raw[n][3] = (ln(nu/nu_c), ln Theta_e, cos theta_B): the network's
+ * (ln j_hat, ln alpha_hat) de-standardised (net, may be NULL) and the exact closure's (exact,
+ * may be NULL), [n][2] each. */
+raptor_status raptor_mlp_closure(raptor_ctx* ctx, int32_t form, const float* raw, int64_t n, float* net,
+                                 float* exact);
 
 /* Resources of the trace-kernel instantiation a plan selects: registers per lane, scratch
  * (spill) bytes per lane and resident work-groups per compute unit at the plan's work-group

@@ -54,7 +54,12 @@ struct TraceParams {
     int n_jobs, max_steps, closure, slow_light;
     int refill_threshold, tile_shift;   // tile width = 1 << tile_shift pixels, height 64 / width
     double eps, M, length_unit, const_j, const_alpha;
+    // learned closure (closure == CL_MLP): FP32 parameters and padded BF16 hi / lo weights
+    const float* mlp_P;
+    const unsigned short* mlp_W;
+    const unsigned short* mlp_Wlo;
 };
 
-enum : int { CL_EXACT = 0, CL_K2_PAPER = 1, CL_CONST = 2, CL_MLP = 3 };
+// CL_MLP evaluates the network in split BF16 form, CL_MLP_BF16 in plain BF16 form
+enum : int { CL_EXACT = 0, CL_K2_PAPER = 1, CL_CONST = 2, CL_MLP = 3, CL_MLP_BF16 = 4 };
 enum : int { RAY_RUNNING = 0, RAY_HORIZON = 1, RAY_ESCAPED = 2, RAY_MAXSTEP = 3, RAY_NUMERIC = 4 };

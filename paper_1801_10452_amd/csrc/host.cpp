@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "context.hpp"
 #include "device_types.hpp"
 #include "ks_geodesic.hpp"
 #include "launch.hpp"
@@ -21,75 +22,7 @@ namespace rt {
 OpTally g_tally;
 }
 
-namespace {
-
-constexpr double kG = 6.67430e-8;
-constexpr double kMsun = 1.98847e33;
-constexpr double kPc = 3.085677581e18;
-constexpr double kC = 2.99792458e10;
-constexpr double kPi = 3.14159265358979323846;
-
-thread_local std::string t_create_error;
-
-template <class T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t cap = 0;
-    hipError_t reserve(size_t n)
-    {
-        if (n <= cap && p) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-        size_t want = std::max<size_t>(n, 1);
-        hipError_t e = hipMalloc(&p, want * sizeof(T));
-        if (e == hipSuccess) cap = want;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-};
-
-}  // namespace
-
-struct raptor_grid {
-    DevGrid d{};
-    void* cells = nullptr;
-    float* x2tab = nullptr;
-    raptor_ctx* owner = nullptr;
-};
-
-struct LaunchPlan {
-    raptor_plan p{256, 0, 1, 8, 2, {0, 0, 0}};
-    int blocks = 0;   // resolved work-group count
-};
-
-struct raptor_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int cu_count = 0;
-    size_t lds_per_block = 65536;
-    std::string err;
-    DevBuf<DevJob> jobs;
-    DevBuf<DevGrid> grids;
-    DevBuf<double> nu, out, pixsr, flux;
-    DevBuf<int> status, steps;
-    DevBuf<unsigned int> counter;
-    DevBuf<unsigned long long> stats;
-    DevBuf<double2> k2;
-    DevBuf<float2> k2f;
-    K2Table k2t{};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<raptor_grid*> live;
-    std::map<int, LaunchPlan> plans;   // key: max_nu * 2 + fp32
-};
-
-namespace {
+namespace rctx {
 
 raptor_status fail(raptor_ctx* ctx, raptor_status s, const std::string& msg)
 {
@@ -103,11 +36,12 @@ raptor_status dev_fail(raptor_ctx* ctx, hipError_t e, const char* what)
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define RAPTOR_CK(call, what)                         \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess) return dev_fail(ctx, e_, what); \
-    } while (0)
+}  // namespace rctx
+
+namespace {
+
+using namespace rctx;
+thread_local std::string t_create_error;
 
 // Table of ln K2(1/Theta) and its derivative in u = ln Theta (d/du ln K2 = x K1/K2 + 2,
 // x = 1/Theta), from the C++17 library Bessel functions; Theta in [1e-2, 1e4].
@@ -151,9 +85,10 @@ raptor_status check_opts(raptor_ctx* ctx, const raptor_opts* o)
     if (o->max_steps < 1) return fail(ctx, RAPTOR_E_INVALID, "max_steps must be >= 1");
     if (o->transfer_prec != RAPTOR_F32 && o->transfer_prec != RAPTOR_F64)
         return fail(ctx, RAPTOR_E_INVALID, "transfer_prec must be RAPTOR_F32 or RAPTOR_F64");
-    if (o->closure < RAPTOR_CLOSURE_EXACT || o->closure > RAPTOR_CLOSURE_MLP)
+    if (o->closure < RAPTOR_CLOSURE_EXACT || o->closure > RAPTOR_CLOSURE_MLP_BF16)
         return fail(ctx, RAPTOR_E_INVALID, "unknown closure");
-    if (o->closure == RAPTOR_CLOSURE_MLP) return fail(ctx, RAPTOR_E_UNSUPPORTED, "MLP closure has no weights loaded");
+    if (o->closure >= RAPTOR_CLOSURE_MLP && !ctx->mlp.ready)
+        return fail(ctx, RAPTOR_E_INVALID, "the MLP closure needs parameters (raptor_mlp_init / set / train)");
     if (o->slow_light != 0 && o->slow_light != 1) return fail(ctx, RAPTOR_E_INVALID, "slow_light must be 0 or 1");
     if (o->mem != RAPTOR_MEM_HOST && o->mem != RAPTOR_MEM_DEVICE) return fail(ctx, RAPTOR_E_INVALID, "unknown mem");
     if (!finite_pos(o->mass_msun) || !finite_pos(o->dist_pc))
@@ -208,15 +143,15 @@ bool plan_valid(const raptor_plan& p)
            (p.min_waves_per_simd >= 1 && p.min_waves_per_simd <= 3);
 }
 
-int plan_key(int n_nu, bool fp32)
+int plan_key(int n_nu, bool fp32, bool mlpc)
 {
     const int nnu = n_nu <= 1 ? 1 : n_nu <= 4 ? 4 : n_nu <= 8 ? 8 : n_nu <= 16 ? 16 : 32;
-    return nnu * 2 + (fp32 ? 1 : 0);
+    return (nnu * 2 + (fp32 ? 1 : 0)) * 2 + (mlpc ? 1 : 0);
 }
 
 // Resolve the work-group count of a plan: blocks_per_cu per compute unit, or as many as are
 // resident at once when 0.
-raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* pl)
+raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* pl, bool mlpc = false)
 {
     // the per-wave sample queue lives in LDS: shrink the work-group until it fits
     while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.threads) > ctx->lds_per_block)
@@ -226,7 +161,7 @@ raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* p
     int per_cu = pl->p.blocks_per_cu;
     if (per_cu == 0) {
         RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &per_cu, trace_kernel_symbol(max_nu, fp32, pl->p.min_waves_per_simd), pl->p.threads,
+                      &per_cu, trace_kernel_symbol(max_nu, fp32, pl->p.min_waves_per_simd, mlpc), pl->p.threads,
                       trace_kernel_lds(max_nu, fp32, pl->p.threads)),
                   "querying occupancy");
         per_cu = std::max(per_cu, 1);
@@ -235,16 +170,16 @@ raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* p
     return RAPTOR_OK;
 }
 
-raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out)
+raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, bool mlpc = false)
 {
-    const int key = plan_key(max_nu, fp32);
+    const int key = plan_key(max_nu, fp32, mlpc);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
         *out = it->second;
         return RAPTOR_OK;
     }
     LaunchPlan pl;
-    raptor_status s = resolve_plan(ctx, max_nu, fp32, &pl);
+    raptor_status s = resolve_plan(ctx, max_nu, fp32, &pl, mlpc);
     if (s != RAPTOR_OK) return s;
     ctx->plans[key] = pl;
     *out = pl;
@@ -257,11 +192,12 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
 {
     const bool dev = o->mem == RAPTOR_MEM_DEVICE;
     const bool fp32 = o->transfer_prec == RAPTOR_F32;
+    const bool mlpc = o->closure >= RAPTOR_CLOSURE_MLP;
     LaunchPlan plan;
     if (force_plan) {
         plan = *force_plan;
     } else {
-        raptor_status ps = plan_for(ctx, n_nu, fp32, &plan);
+        raptor_status ps = plan_for(ctx, n_nu, fp32, &plan, mlpc);
         if (ps != RAPTOR_OK) return ps;
     }
     const int tile_w = plan.p.tile_width, tile_h = 64 / tile_w;
@@ -371,6 +307,9 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     p.length_unit = Lu;
     p.const_j = o->const_j;
     p.const_alpha = o->const_alpha;
+    p.mlp_P = ctx->mlp.P.p;
+    p.mlp_W = ctx->mlp.W.p;
+    p.mlp_Wlo = ctx->mlp.Wlo.p;
     p.refill_threshold = plan.p.refill_threshold;
     p.tile_shift = tile_w == 8 ? 3 : tile_w == 16 ? 4 : tile_w == 32 ? 5 : 6;
 
@@ -494,6 +433,7 @@ void raptor_destroy(raptor_ctx* ctx)
     ctx->stats.release();
     ctx->k2.release();
     ctx->k2f.release();
+    ctx->mlp.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -702,7 +642,7 @@ raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_pr
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
     raptor_status s = resolve_plan(ctx, n_nu, fp32, &pl);
     if (s != RAPTOR_OK) return s;
-    ctx->plans[plan_key(n_nu, fp32)] = pl;
+    ctx->plans[plan_key(n_nu, fp32, false)] = pl;
     return RAPTOR_OK;
 }
 
@@ -723,7 +663,7 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     auto time_plan = [&](const raptor_plan& cand, double* ms) -> raptor_status {
         LaunchPlan pl;
         pl.p = cand;
-        raptor_status r = resolve_plan(ctx, n_nu, fp32, &pl);
+        raptor_status r = resolve_plan(ctx, n_nu, fp32, &pl, o.closure >= RAPTOR_CLOSURE_MLP);
         if (r != RAPTOR_OK) return r;
         double bestv = 1e300;
         for (int i = 0; i < reps; ++i) {
@@ -736,7 +676,7 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
         return RAPTOR_OK;
     };
     LaunchPlan cur;
-    s = plan_for(ctx, n_nu, fp32, &cur);
+    s = plan_for(ctx, n_nu, fp32, &cur, o.closure >= RAPTOR_CLOSURE_MLP);
     if (s != RAPTOR_OK) return s;
     raptor_plan bp = cur.p;
     double bms;
@@ -760,8 +700,9 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     }
     LaunchPlan fin;
     fin.p = bp;
-    if ((s = resolve_plan(ctx, n_nu, fp32, &fin)) != RAPTOR_OK) return s;
-    ctx->plans[plan_key(n_nu, fp32)] = fin;
+    if ((s = resolve_plan(ctx, n_nu, fp32, &fin, o.closure >= RAPTOR_CLOSURE_MLP)) != RAPTOR_OK) return s;
+    const bool mlpc_t = o.closure >= RAPTOR_CLOSURE_MLP;
+    ctx->plans[plan_key(n_nu, fp32, mlpc_t)] = fin;
     if (best) *best = bp;
     if (best_ms) *best_ms = bms;
     return RAPTOR_OK;
@@ -778,7 +719,7 @@ raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
     const bool fp32 = transfer_prec == RAPTOR_F32;
     int regs = 0, spill = 0, maxt = 0, per_cu = 0;
-    RAPTOR_CK(trace_kernel_attributes(n_nu, fp32, plan->min_waves_per_simd, &regs, &spill, &maxt),
+    RAPTOR_CK(trace_kernel_attributes(n_nu, fp32, plan->min_waves_per_simd, false, &regs, &spill, &maxt),
               "reading kernel attributes");
     RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                   &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd), plan->threads,

@@ -10,7 +10,29 @@ hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, in
                         hipStream_t st);
 hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* flux,
                        int max_nu, hipStream_t st);
-hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, int* vgprs, int* spill_bytes, int* max_threads);
-const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe);
+hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int* vgprs, int* spill_bytes,
+                                   int* max_threads);
+// mlpc: the variant with the learned closure (always the uncapped register variant)
+const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = false);
 // dynamic LDS bytes of a trace-kernel work-group of `threads` lanes
 size_t trace_kernel_lds(int max_nu, bool fp32, int threads);
+
+// ---- learned closure (mlp.hip)
+namespace mlp {
+struct Net;
+}
+hipError_t mlp_launch_gen(const K2Table& k2, unsigned long long seed, long long n, float* X, float* T, float* raw,
+                          hipStream_t st);
+hipError_t mlp_launch_exact(const K2Table& k2, long long n, const float* raw, float* out, hipStream_t st);
+// mode 0: MSE gradient against T; mode 1: gradient of sum DY . y
+hipError_t mlp_launch_train(const mlp::Net& net, const float* X, const float* T, const float* DY, long long base,
+                            long long n, int mode, float inv_batch, float* partial, float* loss, int waves,
+                            hipStream_t st);
+// mode 0: Adam + repack; mode 1: summed gradient to grad_out; mode 2: repack only
+hipError_t mlp_launch_reduce(const float* partial, int n_waves, int mode, float* P, float* m, float* v, float lr,
+                             float b1, float b2, float eps, float wd, float bc1, float bc2, float* grad_out,
+                             unsigned short* W, unsigned short* Wlo, unsigned short* WT, hipStream_t st);
+hipError_t mlp_launch_forward(const mlp::Net& net, bool split, const float* X, long long n, float* Y, hipStream_t st);
+hipError_t mlp_launch_forward_f32(const float* P, const float* X, long long n, float* Y, hipStream_t st);
+hipError_t mlp_launch_backward_f32(const float* P, const float* X, const float* DY, long long n, float* G,
+                                   hipStream_t st);

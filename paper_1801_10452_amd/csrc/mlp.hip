@@ -1,0 +1,442 @@
+// mlp.hip -- training and evaluation kernels of the learned closure (see mlp_device.hpp).
+//
+//  gen_kernel        training / validation samples: counter-based SplitMix64 inputs over the
+//                    box and targets from the exact closure (Leung fit, tabulated K2) in the
+//                    log domain, FP64
+//  train_kernel      one wave per 64 samples: forward (split BF16 MFMA), MSE gradient,
+//                    backward (BF16 MFMA) and the wave's partial parameter gradient
+//  reduce_kernel     fixed-order sum of the wave partials; Adam step on the FP32 parameters
+//                    and re-packing of the BF16 hi / lo copies -- or the plain gradient
+//  forward_kernel    batched inference (MFMA), one wave per 64 samples
+//  forward_f32 / backward_f32   FP32 reference path (one thread per sample, no matrix cores)
+#include "launch.hpp"
+#include "mlp_device.hpp"
+#include "plasma.hpp"
+
+namespace mlp {
+namespace {
+
+__device__ inline unsigned long long splitmix(unsigned long long seed, unsigned long long n)
+{
+    unsigned long long z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ inline double uniform01(unsigned long long seed, unsigned long long n)
+{
+    return (double)(splitmix(seed, n) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace
+
+// ln j_hat and ln alpha_hat of the exact closure for raw inputs (ln x, ln Theta, cos), x = nu/nu_c:
+// j / (n_e nu_c J0) = (nu_s/nu_c) / K2(1/Theta) t (t + 2^11/12)^2 exp(-t), t = (x nu_c/nu_s)^1/3,
+// nu_s/nu_c = (2/9) Theta^2 sin(theta_B); alpha_hat = j_hat / (x^2 Theta).
+__device__ inline void exact_targets(const K2Table& k2, double lx, double lth, double cb, double* t0, double* t1)
+{
+    const double th = ::exp(lth);
+    const double sb = ::sqrt(::fmax(1.0 - cb * cb, 0.0));
+    const double ns = (2.0 / 9.0) * th * th * sb;
+    const double t = ::cbrt(::exp(lx) / ns);
+    double lj = ::log(ns) - pl::ln_k2(k2, lth) + ::log(t) + 2.0 * ::log(t + pl::TWO_11_12) - t;
+    lj = ::fmax(lj, LNJ_FLOOR);
+    *t0 = lj;
+    *t1 = lj - 2.0 * lx - lth;
+}
+
+__global__ void gen_kernel(K2Table k2, unsigned long long seed, long long n, float* X, float* T, float* raw)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double u0 = uniform01(seed, 3ull * i), u1 = uniform01(seed, 3ull * i + 1), u2 = uniform01(seed, 3ull * i + 2);
+    const double lx = (double)LX_LO + u0 * ((double)LX_HI - (double)LX_LO);
+    const double lth = (double)LT_LO + u1 * ((double)LT_HI - (double)LT_LO);
+    const double cb = -0.999 + 1.998 * u2;
+    double t0, t1;
+    exact_targets(k2, lx, lth, cb, &t0, &t1);
+    X[3 * i] = norm_lx((float)lx);
+    X[3 * i + 1] = norm_lt((float)lth);
+    X[3 * i + 2] = norm_cb((float)cb);
+    T[2 * i] = (float)((t0 - MU_J) / SIGMA_J);
+    T[2 * i + 1] = (float)((t1 - MU_A) / SIGMA_A);
+    if (raw) {
+        raw[3 * i] = (float)lx;
+        raw[3 * i + 1] = (float)lth;
+        raw[3 * i + 2] = (float)cb;
+    }
+}
+
+// exact targets for given raw inputs (accuracy checks)
+__global__ void exact_kernel(K2Table k2, long long n, const float* raw, float* out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t0, t1;
+    exact_targets(k2, raw[3 * i], raw[3 * i + 1], raw[3 * i + 2], &t0, &t1);
+    out[2 * i] = (float)t0;
+    out[2 * i + 1] = (float)t1;
+}
+
+// ------------------------------------------------------------------------------------------
+// Training: one wave (one work-group) per 64 samples.
+// LDS: Z[4][64][64] pre-activations (BF16, [sample][feature]), two dZ buffers [64][64] (BF16),
+// X[64][16] inputs (BF16).
+// ------------------------------------------------------------------------------------------
+constexpr int TR_LDS = (4 * 64 * 64 + 2 * 64 * 64 + 64 * 16) * 2;
+
+__device__ inline void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ inline void store4(unsigned short* p, float a, float b, float c, float d)
+{
+    *reinterpret_cast<bf16x4*>(p) = pack4(a, b, c, d);
+}
+__device__ inline f32x4 load4(const unsigned short* p)
+{
+    const bf16x4 v = *reinterpret_cast<const bf16x4*>(p);
+    return f32x4{bf2f((unsigned short)v.x), bf2f((unsigned short)v.y), bf2f((unsigned short)v.z),
+                 bf2f((unsigned short)v.w)};
+}
+
+// K = samples fragment of a [sample][feature] BF16 array (row stride rs): lane holds the four
+// samples 16 kt + 4 g + j of feature f0 + n, optionally through the SiLU.
+template <bool ACT>
+__device__ inline bf16x4 frag_samples(const unsigned short* M, int rs, int f0, int kt, int lane)
+{
+    const int n = lane & 15, s0 = 16 * kt + 4 * (lane >> 4);
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float z = bf2f(M[(s0 + j) * rs + f0 + n]);
+        v[j] = ACT ? silu(z) : z;
+    }
+    return pack4(v[0], v[1], v[2], v[3]);
+}
+
+// dW[out][in] (+)= sum_s dZ[s][out] H[s][in] over the wave's 64 samples; writes the wave partial.
+// dZ: [64][64] BF16 (first out_tiles*16 features used); H: [64][rs] BF16 (pre-activations if
+// ACT, raw inputs otherwise); db[out] = sum_s dZ[s][out].
+template <bool ACT>
+__device__ inline void weight_grad(const unsigned short* dZ, const unsigned short* H, int rs, int out_tiles,
+                                   int in_tiles, int out_dim, int in_dim, float* gW, float* gb, int lane)
+{
+    const int g4 = 4 * (lane >> 4), n = lane & 15;
+    for (int mt = 0; mt < out_tiles; ++mt) {
+        bf16x4 a[4];
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) a[kt] = frag_samples<false>(dZ, 64, 16 * mt, kt, lane);
+        for (int nt = 0; nt < in_tiles; ++nt) {
+            f32x4 acc = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) acc = mfma(a[kt], frag_samples<ACT>(H, rs, 16 * nt, kt, lane), acc);
+            const int in = 16 * nt + n;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int out = 16 * mt + g4 + j;
+                if (out < out_dim && in < in_dim) gW[out * in_dim + in] = acc[j];
+            }
+        }
+    }
+    if (lane < out_dim) {
+        float s = 0.0f;
+        for (int smp = 0; smp < 64; ++smp) s += bf2f(dZ[smp * 64 + lane]);
+        gb[lane] = s;
+    }
+}
+
+// dZ_prev[s][in] = (W^T dZ)[in][s] * silu'(Z_prev[s][in]) for the 16 samples of block cb.
+__device__ inline void backprop_block(const unsigned short* WT, int out_pad, int k_tiles, const unsigned short* dZ,
+                                      const unsigned short* Zp, unsigned short* dZp, int cb, int lane)
+{
+    const int g4 = 4 * (lane >> 4), s = 16 * cb + (lane & 15);
+    bf16x4 b[4];
+    for (int kt = 0; kt < k_tiles; ++kt) b[kt] = *reinterpret_cast<const bf16x4*>(dZ + s * 64 + 16 * kt + g4);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = f32x4{0, 0, 0, 0};
+        for (int kt = 0; kt < k_tiles; ++kt) acc = mfma(frag_a(WT, out_pad, 16 * mt, 16 * kt, lane), b[kt], acc);
+        const f32x4 z = load4(Zp + s * 64 + 16 * mt + g4);
+        store4(dZp + s * 64 + 16 * mt + g4, acc.x * silu_grad(z.x), acc.y * silu_grad(z.y), acc.z * silu_grad(z.z),
+               acc.w * silu_grad(z.w));
+    }
+}
+
+// mode 0: gradient of the mean squared error against T (standardised targets), loss sums to
+// loss[wave]; mode 1: gradient of sum dY . y for given dY.
+__global__ void __launch_bounds__(64) train_kernel(Net net, const float* X, const float* T, const float* DY, long long base,
+                                                   long long n, int mode, float inv_batch, float* partial, float* loss)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned short* Z = reinterpret_cast<unsigned short*>(lds);   // [4][64][64]
+    unsigned short* dA = Z + 4 * 64 * 64;                          // [64][64]
+    unsigned short* dB = dA + 64 * 64;                              // [64][64]
+    unsigned short* Xs = dB + 64 * 64;                              // [64][16]
+    const int lane = threadIdx.x;
+    const int g4 = 4 * (lane >> 4), nl = lane & 15;
+    const long long s0 = base + 64ll * blockIdx.x;
+    float* gw = partial + (size_t)blockIdx.x * N_PARAMS;
+    float l0 = 0.0f, l1 = 0.0f;
+
+    // ---- forward of the four column blocks; keep pre-activations, form dY = dZ5
+    for (int cb = 0; cb < 4; ++cb) {
+        const int s = 16 * cb + nl;
+        const long long gs = s0 + s;
+        const bool valid = gs < n;
+        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+        if (valid && lane < 16) {
+            x0 = X[3 * gs];
+            x1 = X[3 * gs + 1];
+            x2 = X[3 * gs + 2];
+        }
+        Split bx;
+        bx.hi = (lane < 16) ? pack4(x0, x1, x2, 0.0f) : bf16x4{0, 0, 0, 0};
+        bx.lo = (lane < 16) ? split4(x0, x1, x2, 0.0f).lo : bf16x4{0, 0, 0, 0};
+        store4(Xs + s * 16 + g4, lane < 16 ? x0 : 0.0f, lane < 16 ? x1 : 0.0f, lane < 16 ? x2 : 0.0f, 0.0f);
+        f32x4 z[16];
+        const f32x4 o = forward_block<true>(net, bx, lane, z);
+#pragma unroll
+        for (int L = 0; L < 4; ++L)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const f32x4 v = z[4 * L + mt];
+                store4(Z + L * 4096 + s * 64 + 16 * mt + g4, v.x, v.y, v.z, v.w);
+            }
+        float d0 = 0.0f, d1 = 0.0f;
+        if (lane < 16 && valid) {
+            if (mode == 0) {
+                const float e0 = o.x - T[2 * gs], e1 = o.y - T[2 * gs + 1];
+                l0 += e0 * e0;
+                l1 += e1 * e1;
+                d0 = e0 * inv_batch;
+                d1 = e1 * inv_batch;
+            } else {
+                d0 = DY[2 * gs];
+                d1 = DY[2 * gs + 1];
+            }
+        }
+        store4(dA + s * 64 + g4, d0, d1, 0.0f, 0.0f);   // dZ5 in features 0..15 (lanes >= 16 write zeros)
+    }
+    lds_sync();
+    // ---- layer 5 (64 -> 2)
+    weight_grad<true>(dA, Z + 3 * 4096, 64, 1, 4, 2, 64, gw + OFF_W5, gw + OFF_B5, lane);
+    for (int cb = 0; cb < 4; ++cb) backprop_block(net.WT + PW5, 16, 1, dA, Z + 3 * 4096, dB, cb, lane);
+    lds_sync();
+    // ---- layers 4, 3, 2
+    unsigned short* cur = dB;
+    unsigned short* nxt = dA;
+    const int offw[3] = {OFF_W4, OFF_W3, OFF_W2}, offb[3] = {OFF_B4, OFF_B3, OFF_B2}, pw[3] = {PW4, PW3, PW2};
+    for (int i = 0; i < 3; ++i) {
+        const int L = 3 - i;   // pre-activation index of this layer's input: Z[L - 1]
+        weight_grad<true>(cur, Z + (L - 1) * 4096, 64, 4, 4, 64, 64, gw + offw[i], gw + offb[i], lane);
+        for (int cb = 0; cb < 4; ++cb) backprop_block(net.WT + pw[i], 64, 4, cur, Z + (L - 1) * 4096, nxt, cb, lane);
+        lds_sync();
+        unsigned short* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    // ---- layer 1 (3 -> 64)
+    weight_grad<false>(cur, Xs, 16, 4, 1, 64, 3, gw + OFF_W1, gw + OFF_B1, lane);
+    if (mode == 0) {
+        for (int o = 32; o > 0; o >>= 1) {
+            l0 += __shfl_xor(l0, o, 64);
+            l1 += __shfl_xor(l1, o, 64);
+        }
+        if (lane == 0) {
+            loss[2 * blockIdx.x] = l0;
+            loss[2 * blockIdx.x + 1] = l1;
+        }
+    }
+}
+
+// Index of parameter p in the padded BF16 layouts (-1 for biases).
+__device__ inline void padded_index(int p, int* iw, int* iwt)
+{
+    int off, in_dim, in_pad, out_pad, pw;
+    if (p < OFF_B1) { off = OFF_W1; in_dim = 3; in_pad = 16; out_pad = 64; pw = PW1; }
+    else if (p >= OFF_W2 && p < OFF_B2) { off = OFF_W2; in_dim = 64; in_pad = 64; out_pad = 64; pw = PW2; }
+    else if (p >= OFF_W3 && p < OFF_B3) { off = OFF_W3; in_dim = 64; in_pad = 64; out_pad = 64; pw = PW3; }
+    else if (p >= OFF_W4 && p < OFF_B4) { off = OFF_W4; in_dim = 64; in_pad = 64; out_pad = 64; pw = PW4; }
+    else if (p >= OFF_W5 && p < OFF_B5) { off = OFF_W5; in_dim = 64; in_pad = 64; out_pad = 16; pw = PW5; }
+    else { *iw = *iwt = -1; return; }
+    const int out = (p - off) / in_dim, in = (p - off) % in_dim;
+    *iw = pw + out * in_pad + in;
+    *iwt = pw + in * out_pad + out;
+}
+
+// mode 0: Adam on P (with moments m, v, step t) then repack; mode 1: grad_out = summed gradient;
+// mode 2: repack only.
+__global__ void reduce_kernel(const float* partial, int n_waves, int mode, float* P, float* m, float* v, float lr,
+                              float b1, float b2, float eps, float wd, float bc1, float bc2, float* grad_out,
+                              unsigned short* W, unsigned short* Wlo, unsigned short* WT)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N_PARAMS) return;
+    if (mode != 2) {
+        float g = 0.0f;
+        for (int w = 0; w < n_waves; ++w) g += partial[(size_t)w * N_PARAMS + p];
+        if (mode == 1) {
+            grad_out[p] = g;
+            return;
+        }
+        const float mm = b1 * m[p] + (1.0f - b1) * g;
+        const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+        m[p] = mm;
+        v[p] = vv;
+        P[p] -= lr * ((mm / bc1) / (sqrtf(vv / bc2) + eps) + wd * P[p]);
+    }
+    int iw, iwt;
+    padded_index(p, &iw, &iwt);
+    if (iw >= 0) {
+        const float w = P[p];
+        const unsigned short hi = f2bf(w);
+        W[iw] = hi;
+        Wlo[iw] = f2bf(w - bf2f(hi));
+        WT[iwt] = hi;
+    }
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(64) forward_kernel(Net net, const float* X, long long n, float* Y)
+{
+    const long long i = 64ll * blockIdx.x + threadIdx.x;
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (i < n) {
+        x0 = X[3 * i];
+        x1 = X[3 * i + 1];
+        x2 = X[3 * i + 2];
+    }
+    float y0, y1;
+    forward_wave<SPLIT>(net, x0, x1, x2, &y0, &y1);
+    if (i < n) {
+        Y[2 * i] = y0;
+        Y[2 * i + 1] = y1;
+    }
+}
+
+// ---- FP32 reference path (no matrix cores) ------------------------------------------------
+__device__ inline void f32_forward(const float* P, const float* x, float z[4][64], float h[5][64], float y[2])
+{
+    const int dims[6] = {3, 64, 64, 64, 64, 2};
+    const int offs[5] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4, OFF_W5};
+    for (int i = 0; i < 3; ++i) h[0][i] = x[i];
+    for (int L = 0; L < 5; ++L) {
+        const int ni = dims[L], no = dims[L + 1];
+        const float* W = P + offs[L];
+        const float* b = W + no * ni;
+        for (int o = 0; o < no; ++o) {
+            float s = b[o];
+            for (int i = 0; i < ni; ++i) s += W[o * ni + i] * h[L][i];
+            if (L < 4) {
+                z[L][o] = s;
+                h[L + 1][o] = silu(s);
+            } else {
+                y[o] = s;
+            }
+        }
+    }
+}
+
+__global__ void forward_f32_kernel(const float* P, const float* X, long long n, float* Y)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float z[4][64], h[5][64], y[2];
+    f32_forward(P, X + 3 * i, z, h, y);
+    Y[2 * i] = y[0];
+    Y[2 * i + 1] = y[1];
+}
+
+__global__ void backward_f32_kernel(const float* P, const float* X, const float* DY, long long n, float* G)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float z[4][64], h[5][64], y[2];
+    f32_forward(P, X + 3 * i, z, h, y);
+    const int dims[6] = {3, 64, 64, 64, 64, 2};
+    const int offs[5] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4, OFF_W5};
+    float g[64], gp[64];
+    g[0] = DY[2 * i];
+    g[1] = DY[2 * i + 1];
+    for (int L = 4; L >= 0; --L) {
+        const int ni = dims[L], no = dims[L + 1];
+        const float* W = P + offs[L];
+        float* gW = G + offs[L];
+        float* gb = gW + no * ni;
+        for (int o = 0; o < no; ++o) {
+            atomicAdd(&gb[o], g[o]);
+            for (int k = 0; k < ni; ++k) atomicAdd(&gW[o * ni + k], g[o] * h[L][k]);
+        }
+        if (L == 0) break;
+        for (int k = 0; k < ni; ++k) {
+            float s = 0.0f;
+            for (int o = 0; o < no; ++o) s += W[o * ni + k] * g[o];
+            gp[k] = s * silu_grad(z[L - 1][k]);
+        }
+        for (int k = 0; k < ni; ++k) g[k] = gp[k];
+    }
+}
+
+}  // namespace mlp
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+hipError_t mlp_launch_gen(const K2Table& k2, unsigned long long seed, long long n, float* X, float* T, float* raw,
+                          hipStream_t st)
+{
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(mlp::gen_kernel, dim3(blocks), dim3(256), 0, st, k2, seed, n, X, T, raw);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_exact(const K2Table& k2, long long n, const float* raw, float* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp::exact_kernel, dim3((int)((n + 255) / 256)), dim3(256), 0, st, k2, n, raw, out);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_train(const mlp::Net& net, const float* X, const float* T, const float* DY, long long base,
+                            long long n, int mode, float inv_batch, float* partial, float* loss, int waves,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp::train_kernel, dim3(waves), dim3(64), mlp::TR_LDS, st, net, X, T, DY, base, n, mode,
+                       inv_batch, partial, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_reduce(const float* partial, int n_waves, int mode, float* P, float* m, float* v, float lr,
+                             float b1, float b2, float eps, float wd, float bc1, float bc2, float* grad_out,
+                             unsigned short* W, unsigned short* Wlo, unsigned short* WT, hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp::reduce_kernel, dim3((mlp::N_PARAMS + 255) / 256), dim3(256), 0, st, partial, n_waves, mode,
+                       P, m, v, lr, b1, b2, eps, wd, bc1, bc2, grad_out, W, Wlo, WT);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_forward(const mlp::Net& net, bool split, const float* X, long long n, float* Y, hipStream_t st)
+{
+    const int blocks = (int)((n + 63) / 64);
+    if (split)
+        hipLaunchKernelGGL(mlp::forward_kernel<true>, dim3(blocks), dim3(64), 0, st, net, X, n, Y);
+    else
+        hipLaunchKernelGGL(mlp::forward_kernel<false>, dim3(blocks), dim3(64), 0, st, net, X, n, Y);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_forward_f32(const float* P, const float* X, long long n, float* Y, hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp::forward_f32_kernel, dim3((int)((n + 63) / 64)), dim3(64), 0, st, P, X, n, Y);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_backward_f32(const float* P, const float* X, const float* DY, long long n, float* G,
+                                   hipStream_t st)
+{
+    hipLaunchKernelGGL(mlp::backward_f32_kernel, dim3((int)((n + 63) / 64)), dim3(64), 0, st, P, X, DY, n, G);
+    return hipGetLastError();
+}

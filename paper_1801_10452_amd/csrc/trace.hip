@@ -11,6 +11,7 @@
 #include "ks_geodesic.hpp"
 #include "plasma.hpp"
 #include "launch.hpp"
+#include "mlp_device.hpp"
 
 namespace {
 
@@ -171,7 +172,63 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
     return zamo;
 }
 
-template <int NNU, class TT, int WPE>
+// Learned-closure variant of eval_sample for one round: every lane of the wave takes part in the
+// network evaluations (one per frequency); lanes without a sample feed zeros.  Samples whose
+// closure inputs leave the training box use the exact closure.
+template <int NNU, class TT>
+__device__ inline void eval_round_mlp(const TraceParams& p, bool has, const double* q, const LaneInfo& li, TT* A,
+                                      TT* dtau, unsigned long long& c_zamo, unsigned long long& c_fallback)
+{
+    double fl[4] = {0.0, 1.0, 1.0, 0.0};
+    double nr = 1.0, cb = 0.0;
+    bool zamo = false;
+    Transfer<TT> tr;
+    tr.emits = false;
+    if (has) {
+        const DevGrid& G = p.grids[li.grid];
+        const double y[8] = {q[0], q[1], q[2], q[3], q[4], q[5], 0.0, q[6]};
+        pl::sample_fluid(G, p.slow_light, li.fast_snap, y, fl);
+        zamo = pl::fluid_frame(li.a, li.a * li.a, p.M, y, q[8], q[9], fl[3], &nr, &cb);
+        tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+    }
+    c_zamo += __popcll(__ballot(zamo));
+    const mlp::Net net{p.mlp_P, p.mlp_W, p.mlp_Wlo, nullptr};
+    const double nuc = pl::NUC_PER_GAUSS * fl[2];
+    const float lth = (float)::log(fl[1] > 0.0 ? fl[1] : 1.0);
+    const double ds = nr * q[7] * p.length_unit;
+    const double inr3 = has ? rt::rcp_nr(nr * nr * nr) : 0.0;
+#pragma unroll 1
+    for (int f = 0; f < NNU; ++f) {
+        const bool act = has && f < li.n_nu;
+        const double nu = act ? p.nu[li.nu_base + f] * nr : nuc;
+        const float lx = (float)::log(nu / nuc);
+        const bool inb = act && tr.emits && mlp::in_box(lx, lth, (float)cb);
+        c_fallback += __popcll(__ballot(act && tr.emits && !inb));
+        const float x0 = inb ? mlp::norm_lx(lx) : 0.0f, x1 = inb ? mlp::norm_lt(lth) : 0.0f,
+                    x2 = inb ? mlp::norm_cb((float)cb) : 0.0f;
+        float y0, y1;
+        if (p.closure == CL_MLP_BF16)
+            mlp::forward_wave<false>(net, x0, x1, x2, &y0, &y1);
+        else
+            mlp::forward_wave<true>(net, x0, x1, x2, &y0, &y1);
+        if (!act) continue;
+        A[f] = TT(0);
+        dtau[f] = TT(0);
+        if (inb) {
+            const TT lnj = (TT)(y0 * mlp::SIGMA_J + mlp::MU_J), lna = (TT)(y1 * mlp::SIGMA_A + mlp::MU_A);
+            const TT ne = (TT)fl[0], nucT = (TT)nuc;
+            const TT j = ne * nucT * (TT)pl::J_PREF * rt::exp_(lnj);
+            const TT yy = (TT)(pl::H_OVER_MEC2 * nu / fl[1]);
+            const TT planck = (yy > TT(1e-4)) ? rt::expm1_(yy) / yy : TT(1) + TT(0.5) * yy;   // B_RJ / B_nu
+            const TT al = ne * (TT)pl::J_PREF / (TT(2.0 * pl::ME_CGS) * nucT) * rt::exp_(lna) * planck;
+            pl::step_source(j, al, j / al, (TT)ds, (TT)inr3, A[f], dtau[f]);
+        } else if (tr.emits) {
+            tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
+        }
+    }
+}
+
+template <int NNU, class TT, int WPE, bool MLPC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(WPE, 8)))
 trace_kernel(TraceParams p)
 {
@@ -199,7 +256,7 @@ trace_kernel(TraceParams p)
 
     // wave-level statistics (ballot counts: scalar registers)
     unsigned long long c_rays = 0, c_steps = 0, c_samples = 0, c_hor = 0, c_esc = 0, c_max = 0, c_pole = 0,
-                       c_num = 0, c_zamo = 0;
+                       c_num = 0, c_zamo = 0, c_fallback = 0;
 
     long long next = 0, end = 0;   // rays of the current tile not yet handed out (wave-uniform)
     bool drained = false;
@@ -320,21 +377,39 @@ trace_kernel(TraceParams p)
             wave_lds_sync();
             for (unsigned r0 = 0; r0 < total; r0 += 64) {
                 const unsigned i = r0 + lane;
-                bool zamo = false;
-                if (i < total) {
-                    const int s = slot_map[i];
+                if (MLPC) {
+                    // every lane takes part in the network evaluations of the round
+                    const bool has = i < total;
+                    const int s = has ? slot_map[i] : 0;
                     double q[N_FIELDS];
 #pragma unroll
-                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * Q::SLOTS + s] : 1.0;
                     TT A[NNU], dt[NNU];
-                    zamo = eval_sample<NNU, TT>(p, q, info[s / K], A, dt);
+                    eval_round_mlp<NNU, TT>(p, has, q, info[s / K], A, dt, c_zamo, c_fallback);
+                    if (has) {
 #pragma unroll
-                    for (int f = 0; f < NNU; ++f) {
-                        res[s * 2 * NNU + f] = A[f];
-                        res[s * 2 * NNU + NNU + f] = dt[f];
+                        for (int f = 0; f < NNU; ++f) {
+                            res[s * 2 * NNU + f] = A[f];
+                            res[s * 2 * NNU + NNU + f] = dt[f];
+                        }
                     }
+                } else {
+                    bool zamo = false;
+                    if (i < total) {
+                        const int s = slot_map[i];
+                        double q[N_FIELDS];
+#pragma unroll
+                        for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                        TT A[NNU], dt[NNU];
+                        zamo = eval_sample<NNU, TT>(p, q, info[s / K], A, dt);
+#pragma unroll
+                        for (int f = 0; f < NNU; ++f) {
+                            res[s * 2 * NNU + f] = A[f];
+                            res[s * 2 * NNU + NNU + f] = dt[f];
+                        }
+                    }
+                    c_zamo += __popcll(__ballot(zamo));
                 }
-                c_zamo += __popcll(__ballot(zamo));
             }
             c_samples += total;
             wave_lds_sync();
@@ -380,7 +455,7 @@ trace_kernel(TraceParams p)
     // ------------------------------------------------------------ statistics, one atomic per counter per wave
     if (lane == 0) {
         const unsigned long long st[ST_COUNT] = {c_rays, c_steps, c_samples, c_hor, c_esc, c_max, c_pole, c_num,
-                                                 0ull, c_zamo};
+                                                 c_fallback, c_zamo};
 #pragma unroll
         for (int i = 0; i < ST_COUNT; ++i)
             if (st[i]) atomicAdd(p.stats + i, st[i]);
@@ -419,20 +494,21 @@ __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* sta
 }
 
 template <int NNU, class TT>
-const void* symbol_of(int wpe)
+const void* symbol_of(int wpe, bool mlpc)
 {
-    return wpe >= 3 ? (const void*)trace_kernel<NNU, TT, 3>
-         : wpe == 2 ? (const void*)trace_kernel<NNU, TT, 2> : (const void*)trace_kernel<NNU, TT, 1>;
+    if (mlpc) return (const void*)trace_kernel<NNU, TT, 1, true>;
+    return wpe >= 3 ? (const void*)trace_kernel<NNU, TT, 3, false>
+         : wpe == 2 ? (const void*)trace_kernel<NNU, TT, 2, false> : (const void*)trace_kernel<NNU, TT, 1, false>;
 }
 
 template <class TT>
-const void* symbol_tt(int max_nu, int wpe)
+const void* symbol_tt(int max_nu, int wpe, bool mlpc)
 {
-    if (max_nu <= 1) return symbol_of<1, TT>(wpe);
-    if (max_nu <= 4) return symbol_of<4, TT>(wpe);
-    if (max_nu <= 8) return symbol_of<8, TT>(wpe);
-    if (max_nu <= 16) return symbol_of<16, TT>(wpe);
-    return symbol_of<32, TT>(wpe);
+    if (max_nu <= 1) return symbol_of<1, TT>(wpe, mlpc);
+    if (max_nu <= 4) return symbol_of<4, TT>(wpe, mlpc);
+    if (max_nu <= 8) return symbol_of<8, TT>(wpe, mlpc);
+    if (max_nu <= 16) return symbol_of<16, TT>(wpe, mlpc);
+    return symbol_of<32, TT>(wpe, mlpc);
 }
 
 }  // namespace
@@ -445,7 +521,7 @@ hipError_t launch_reset(unsigned int* tile_counter, unsigned long long* stats, h
 
 hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, int blocks, int threads, hipStream_t st)
 {
-    const void* fn = trace_kernel_symbol(max_nu, fp32, wpe);
+    const void* fn = trace_kernel_symbol(max_nu, fp32, wpe, p.closure >= CL_MLP);
     void* args[] = {const_cast<TraceParams*>(&p)};
     return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, trace_kernel_lds(max_nu, fp32, threads), st);
 }
@@ -471,15 +547,16 @@ size_t trace_kernel_lds(int max_nu, bool fp32, int threads)
     return waves * (fp32 ? per(0.0f) : per(0.0));
 }
 
-const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe)
+const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc)
 {
-    return fp32 ? symbol_tt<float>(max_nu, wpe) : symbol_tt<double>(max_nu, wpe);
+    return fp32 ? symbol_tt<float>(max_nu, wpe, mlpc) : symbol_tt<double>(max_nu, wpe, mlpc);
 }
 
-hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, int* vgprs, int* spill_bytes, int* max_threads)
+hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int* vgprs, int* spill_bytes,
+                                   int* max_threads)
 {
     hipFuncAttributes at;
-    const hipError_t e = hipFuncGetAttributes(&at, trace_kernel_symbol(max_nu, fp32, wpe));
+    const hipError_t e = hipFuncGetAttributes(&at, trace_kernel_symbol(max_nu, fp32, wpe, mlpc));
     if (e != hipSuccess) return e;
     if (vgprs) *vgprs = at.numRegs;
     if (spill_bytes) *spill_bytes = (int)at.localSizeBytes;

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(PKG, "libraptor_hip.so")
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_RANGE = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-CLOSURE_EXACT, CLOSURE_K2_PAPER, CLOSURE_CONST, CLOSURE_MLP = 0, 1, 2, 3
+CLOSURE_EXACT, CLOSURE_K2_PAPER, CLOSURE_CONST, CLOSURE_MLP, CLOSURE_MLP_BF16 = 0, 1, 2, 3, 4
+MLP_SPLIT, MLP_BF16, MLP_F32 = 0, 1, 2
+MLP_PARAMS = 12866
 RAY_HORIZON, RAY_ESCAPED, RAY_MAXSTEP, RAY_NUMERIC = 1, 2, 3, 4
 MAX_NU = 32
 
@@ -68,11 +70,29 @@ class CPlan(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class CMlpCfg(C.Structure):
+    _fields_ = [("n_train", C.c_int64), ("n_val", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32),
+                ("lr", C.c_float), ("lr_final", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("adam_eps", C.c_float), ("weight_decay", C.c_float), ("train_seed", C.c_uint64),
+                ("val_seed", C.c_uint64), ("form", C.c_int32), ("reserved", C.c_int32)]
+
+
+class CMlpReport(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("train_loss", C.c_double), ("val_rms", C.c_double * 2),
+                ("val_max", C.c_double * 2), ("val_rms_bright", C.c_double), ("train_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"steps": self.steps, "train_loss": self.train_loss, "val_rms": list(self.val_rms),
+                "val_max": list(self.val_max), "val_rms_bright": self.val_rms_bright, "train_ms": self.train_ms}
+
+
 # every symbol include/raptor.h declares
 EXPORTS = ["raptor_create", "raptor_destroy", "raptor_last_error", "raptor_grid_upload", "raptor_grid_release",
            "raptor_default_opts", "raptor_trace_image", "raptor_trace_spectrum", "raptor_trace_spectrum_ex",
            "raptor_trace_batch", "raptor_work_per_unit", "raptor_get_plan", "raptor_set_plan",
-           "raptor_autotune_batch", "raptor_kernel_info"]
+           "raptor_autotune_batch", "raptor_kernel_info", "raptor_mlp_default_cfg", "raptor_mlp_init",
+           "raptor_mlp_train", "raptor_mlp_get_params", "raptor_mlp_set_params", "raptor_mlp_get_weights",
+           "raptor_mlp_set_weights", "raptor_mlp_forward", "raptor_mlp_backward", "raptor_mlp_closure"]
 
 _lib = None
 
@@ -116,6 +136,17 @@ def lib():
         L.raptor_autotune_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
                                             C.c_int32, C.c_int32, C.POINTER(CPlan), DP]
         L.raptor_kernel_info.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan), IP, IP, IP]
+        FP = C.POINTER(C.c_float)
+        L.raptor_mlp_default_cfg.argtypes = [C.POINTER(CMlpCfg)]
+        L.raptor_mlp_init.argtypes = [V, C.c_uint64]
+        L.raptor_mlp_train.argtypes = [V, C.POINTER(CMlpCfg), C.POINTER(CMlpReport)]
+        L.raptor_mlp_get_params.argtypes = [V, FP, C.c_int32]
+        L.raptor_mlp_set_params.argtypes = [V, FP, C.c_int32]
+        L.raptor_mlp_get_weights.argtypes = [V, V, C.POINTER(C.c_size_t)]
+        L.raptor_mlp_set_weights.argtypes = [V, V, C.c_size_t]
+        L.raptor_mlp_forward.argtypes = [V, C.c_int32, FP, C.c_int64, FP]
+        L.raptor_mlp_backward.argtypes = [V, C.c_int32, FP, FP, C.c_int64, FP]
+        L.raptor_mlp_closure.argtypes = [V, C.c_int32, FP, C.c_int64, FP, FP]
         for name in EXPORTS:
             if name not in ("raptor_destroy", "raptor_last_error", "raptor_grid_release"):
                 getattr(L, name).restype = C.c_int
@@ -297,6 +328,81 @@ def kernel_info(ctx, n_nu, prec, plan):
     v = [C.c_int32() for _ in range(3)]
     ctx._check(lib().raptor_kernel_info(ctx.h, n_nu, prec, C.byref(plan), *[C.byref(x) for x in v]))
     return {"vgprs": v[0].value, "scratch_bytes": v[1].value, "blocks_per_cu": v[2].value}
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mlp_default_cfg(**kw) -> CMlpCfg:
+    c = CMlpCfg()
+    lib().raptor_mlp_default_cfg(C.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def mlp_init(ctx, seed=1801104520 + 102):
+    ctx._check(lib().raptor_mlp_init(ctx.h, seed))
+
+
+def mlp_train(ctx, cfg=None):
+    cfg = cfg or mlp_default_cfg()
+    rep = CMlpReport()
+    ctx._check(lib().raptor_mlp_train(ctx.h, C.byref(cfg), C.byref(rep)))
+    return rep
+
+
+def mlp_get_params(ctx):
+    out = np.zeros(MLP_PARAMS, dtype=np.float32)
+    ctx._check(lib().raptor_mlp_get_params(ctx.h, _fp(out), MLP_PARAMS))
+    return out
+
+
+def mlp_set_params(ctx, params):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    ctx._check(lib().raptor_mlp_set_params(ctx.h, _fp(params), params.size))
+
+
+def mlp_get_weights(ctx) -> bytes:
+    n = C.c_size_t(0)
+    ctx._check(lib().raptor_mlp_get_weights(ctx.h, None, C.byref(n)))
+    buf = (C.c_char * n.value)()
+    ctx._check(lib().raptor_mlp_get_weights(ctx.h, buf, C.byref(n)))
+    return bytes(buf)
+
+
+def mlp_set_weights(ctx, blob: bytes):
+    buf = C.create_string_buffer(blob, len(blob))
+    ctx._check(lib().raptor_mlp_set_weights(ctx.h, buf, len(blob)))
+
+
+def mlp_forward(ctx, x, form=MLP_SPLIT):
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+    y = np.zeros((x.shape[0], 2), dtype=np.float32)
+    ctx._check(lib().raptor_mlp_forward(ctx.h, form, _fp(x), x.shape[0], _fp(y)))
+    return y
+
+
+def mlp_backward(ctx, x, dy, form=MLP_BF16):
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+    dy = np.ascontiguousarray(dy, dtype=np.float32).reshape(-1, 2)
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    ctx._check(lib().raptor_mlp_backward(ctx.h, form, _fp(x), _fp(dy), x.shape[0], _fp(g)))
+    return g
+
+
+def mlp_closure(ctx, raw, form=MLP_SPLIT, net=True, exact=True):
+    """(network, exact) (ln j_hat, ln alpha_hat) for raw inputs (ln(nu/nu_c), ln Theta_e, cos)."""
+    raw = np.ascontiguousarray(raw, dtype=np.float32).reshape(-1, 3)
+    n = raw.shape[0]
+    out_n = np.zeros((n, 2), dtype=np.float32) if net else None
+    out_e = np.zeros((n, 2), dtype=np.float32) if exact else None
+    ctx._check(lib().raptor_mlp_closure(ctx.h, form, _fp(raw), n, _fp(out_n) if net else None,
+                                        _fp(out_e) if exact else None))
+    return out_n, out_e
 
 
 def split_batch_images(images, cams, n_nu):

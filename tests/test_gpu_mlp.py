@@ -1,0 +1,122 @@
+"""The learned closure on the GPU (through the C ABI) against the CPU oracle.
+
+* forward and backward of the network in FP32, split-BF16 and plain-BF16 forms against the
+  oracle's float64 network at the same parameters;
+* the on-device training targets against the oracle's exact closure;
+* a short training run, checkpoint round trip, and the network inside the trace kernel.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+J0 = math.sqrt(2) * math.pi * 4.80320471e-10 ** 2 / (3 * 2.99792458e10)
+NUC_PER_G = 4.80320471e-10 / (2 * math.pi * 9.1093837015e-28 * 2.99792458e10)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1801_10452_amd import raptor
+    return raptor
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def random_params(orc, seed, scale):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(0, scale, orc.mlp_param_count())).astype(np.float32)
+
+
+def test_forward_matches_oracle(R, ctx, orc):
+    P = random_params(orc, 1, 0.15)
+    R.mlp_set_params(ctx, P)
+    x = np.random.default_rng(2).uniform(-1, 1, (1000, 3)).astype(np.float32)
+    ref = orc.mlp_forward(P.astype(np.float64), x.astype(np.float64))
+    scale = np.abs(ref).max()
+    for form, tol in [(R.MLP_F32, 2e-5), (R.MLP_SPLIT, 2e-3), (R.MLP_BF16, 5e-2)]:
+        y = R.mlp_forward(ctx, x, form)
+        err = np.abs(y - ref).max() / scale
+        print(f"[mlp forward form={form}] max err / scale = {err:.3e}", flush=True)
+        assert err <= tol
+
+
+def test_backward_matches_oracle(R, ctx, orc):
+    P = random_params(orc, 3, 0.15)
+    R.mlp_set_params(ctx, P)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, (333, 3)).astype(np.float32)
+    dy = rng.normal(0, 1, (333, 2)).astype(np.float32)
+    ref = orc.mlp_backward(P.astype(np.float64), x.astype(np.float64), dy.astype(np.float64))
+    for form, tol in [(R.MLP_F32, 1e-4), (R.MLP_BF16, 3e-2)]:
+        g = R.mlp_backward(ctx, x, dy, form).astype(np.float64)
+        rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        cos = g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref))
+        print(f"[mlp backward form={form}] rel l2 err {rel:.3e} cosine {cos:.6f}", flush=True)
+        assert rel <= tol and cos >= 1 - tol
+
+
+def test_training_targets_match_oracle_closure(R, ctx, orc):
+    """ln j_hat of the exact closure on the device = ln(j / (n_e nu_c J0)) of the oracle."""
+    raw = S.mlp_samples(400, seed=S.S0 + 7).astype(np.float32)
+    _, ex = R.mlp_closure(ctx, raw, net=False)
+    B, ne = 10.0, 1.0
+    nuc = NUC_PER_G * B
+    n_cmp = 0
+    for i in range(raw.shape[0]):
+        lx, lt, cb = (float(v) for v in raw[i])
+        j, a = orc.closure(math.exp(lx) * nuc, ne, math.exp(lt), B, cb)
+        if j <= 0 or math.log(j / (ne * nuc * J0)) < -39.0:
+            assert ex[i, 0] == pytest.approx(-40.0, abs=1e-3) or (j > 0 and ex[i, 0] < -38.0)
+            continue
+        lnj = math.log(j / (ne * nuc * J0))
+        assert ex[i, 0] == pytest.approx(lnj, abs=2e-4 * max(1.0, abs(lnj)))
+        # Rayleigh-Jeans absorption in units of n_e J0 / (2 m_e nu_c): alpha_hat = j_hat / (x^2 Theta)
+        assert ex[i, 1] == pytest.approx(lnj - 2 * lx - lt, abs=2e-4 * max(1.0, abs(lnj - 2 * lx - lt)))
+        n_cmp += 1
+    assert n_cmp > 200
+
+
+def test_short_training_and_checkpoint(R, ctx):
+    R.mlp_init(ctx)
+    cfg = R.mlp_default_cfg(n_train=262144, n_val=20000, epochs=3, batch=4096, lr=3e-3)
+    rep0 = R.mlp_train(ctx, R.mlp_default_cfg(n_train=262144, n_val=20000, epochs=1, batch=4096, lr=1e-9,
+                                              lr_final=1e-9))
+    rep = R.mlp_train(ctx, cfg)
+    print(f"[mlp short training] before {rep0.as_dict()}\n[mlp short training] after {rep.as_dict()}", flush=True)
+    assert np.isfinite(rep.train_loss) and rep.val_rms[0] < 0.5 * rep0.val_rms[0]
+    blob = R.mlp_get_weights(ctx)
+    x = np.random.default_rng(5).uniform(-1, 1, (256, 3)).astype(np.float32)
+    y1 = R.mlp_forward(ctx, x, R.MLP_SPLIT)
+    c2 = R.Context(0)
+    R.mlp_set_weights(c2, blob)
+    assert np.array_equal(R.mlp_forward(c2, x, R.MLP_SPLIT), y1)
+    assert np.array_equal(R.mlp_get_params(c2), R.mlp_get_params(ctx))
+    c2.close()
+    with pytest.raises(R.RaptorError):
+        R.mlp_set_weights(ctx, blob[:-4])
+
+
+def test_mlp_closure_in_trace_kernel(R, ctx):
+    """The trace kernel with the learned closure runs, reports its exact-closure fallbacks and
+    gives the same image as the exact closure up to the network's error."""
+    if not R.mlp_get_params(ctx).any():
+        R.mlp_init(ctx)
+    cam, g, nu = S.small_image()
+    gh = ctx.upload_grid(g)
+    ex, fx, sx = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32))
+    for cl in (R.CLOSURE_MLP, R.CLOSURE_MLP_BF16):
+        im, fm, sm = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32, closure=cl))
+        print(f"[mlp trace closure={cl}] flux exact {fx[0]:.6e} mlp {fm[0]:.6e} rel {fm[0] / fx[0] - 1:+.3e} "
+              f"fallback {sm.n_mlp_fallback} samples {sm.samples}", flush=True)
+        assert sm.ray_steps == sx.ray_steps and sm.samples == sx.samples
+        assert np.isfinite(im).all() and fm[0] > 0
+    ctx.release_grid(gh)
