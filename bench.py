@@ -1,16 +1,21 @@
 """Benchmark of the ray-tracing hot path on one MI355X.
 
-One step = one persistent batched launch that traces the production workload through the C
-ABI: 9 images of 512 x 512 pixels (spins {0, 0.5, 0.9375} x inclinations {30, 60, 85} deg),
-camera at r = 1e4 M with a +-20 M field of view, 230 GHz, on seeded synthetic float32
-256 x 256 MKS fluid grids (one per spin), FP64 geodesics with FP32 transfer (or FP64 with
---prec f64).  Inputs are resident in device memory before timing starts and outputs stay in
-device memory.  Prints one JSON line.
+One step = one batched call through the C ABI over the production workload: 9 images of
+512 x 512 pixels (spins {0, 0.5, 0.9375} x inclinations {30, 60, 85} deg), camera at
+r = 1e4 M with a +-20 M field of view, 230 GHz, on seeded synthetic float32 256 x 256 MKS fluid
+grids (one per spin), FP64 geodesics with FP32 transfer (or FP64 with --prec f64), replayed as
+a HIP graph (reset, persistent trace kernel, flux reduction).  Inputs are resident in device
+memory before timing starts and outputs stay in device memory.
+
+Two forms run on the same GPU: the plain method (exact thermal-synchrotron closure) gives the
+headline value; the learned closure (network trained on the device by the library's own
+kernels before timing) is reported beside it with its total-flux error against the plain form.
+Prints one JSON line.
 """
 import argparse
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
@@ -20,9 +25,10 @@ sys.path.insert(0, ROOT)
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 
 
-def cpu_baseline(sets, opts_gpu, budget_s=12.0):
+def cpu_baseline(sets, opts_gpu, budget_s=15.0):
     """The oracle on this host's cores over a bounded, strided pixel sample of the same
-    workload: ray-steps per second."""
+    workload (chunks of 64 rays per image until the time budget is spent): ray-steps per
+    second."""
     import numpy as np
     from oracle import oracle as O
     import synthetic as S
@@ -32,14 +38,15 @@ def cpu_baseline(sets, opts_gpu, budget_s=12.0):
     env_threads = os.environ.get("OMP_NUM_THREADS")
     if env_threads and env_threads.isdigit():
         threads = min(threads, int(env_threads))
+    handles = {id(g): O.GridHandle(g) for _, g in sets}
     steps = 0
     rays = 0
     t0 = time.perf_counter()
     chunk = 0
-    while time.perf_counter() - t0 < budget_s and chunk < 64:
+    while time.perf_counter() - t0 < budget_s and chunk < 4096:
         for k, (cam, g) in enumerate(sets):
             pix = np.arange(chunk * 97 + k, cam.nx * cam.ny, 4099, dtype=np.int64)[:64]
-            _, st = O.trace_pixels(cam, O.GridHandle(g), oo, [S.NU_230], pix, n_threads=threads)
+            _, st = O.trace_pixels(cam, handles[id(g)], oo, [S.NU_230], pix, n_threads=threads)
             steps += int(st[:, 1].sum())
             rays += pix.size
         chunk += 1
@@ -49,13 +56,39 @@ def cpu_baseline(sets, opts_gpu, budget_s=12.0):
                       f"workload), {steps} ray-steps in {dt:.1f} s, FP64, 230 GHz"}
 
 
+def time_form(ctx, R, cams, grids, nu, opts, images, flux, steps, warmup):
+    import torch
+
+    def step():
+        return ctx.trace_batch(cams, grids, nu, opts, images=images, flux=flux)[2]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"ms": dt * 1e3 / steps,
+            "ray_steps": sum(s.ray_steps for s in stats) / steps,
+            "samples": sum(s.samples for s in stats) / steps,
+            "fallback": sum(s.n_mlp_fallback for s in stats) / steps,
+            "kernel_ms": sum(s.kernel_ms for s in stats) / steps,
+            "kernel_ms_median": statistics.median(s.kernel_ms for s in stats),
+            "flux": flux.detach().cpu().numpy().ravel().copy()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--res", type=int, default=512)
+    ap.add_argument("--launch", choices=["graph", "direct"], default="graph")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "trace_kernel_traffic.json"))
     ap.add_argument("--copy-calibration", action="store_true",
@@ -75,6 +108,7 @@ def main():
                                    "in DESIGN.md but not launched"}))
         sys.exit(2)
 
+    import numpy as np
     import torch
     import synthetic as S
     from paper_1801_10452_amd import raptor as R
@@ -87,42 +121,31 @@ def main():
         if id(g) not in handles:
             handles[id(g)] = ctx.upload_grid(g)
         grids.append(handles[id(g)])
-    opts = R.default_opts(transfer_prec=R.F32 if args.prec == "f32" else R.F64, mem=R.MEM_DEVICE)
+    prec = R.F32 if args.prec == "f32" else R.F64
+    launch = R.LAUNCH_GRAPH if args.launch == "graph" else R.LAUNCH_DIRECT
     n_pix = sum(c.nx * c.ny for c in cams)
     images = torch.empty(n_pix, dtype=torch.float64, device="cuda")
     flux = torch.empty((len(cams), 1), dtype=torch.float64, device="cuda")
+    nu = [S.NU_230]
     torch.cuda.synchronize()
 
-    def step():
-        return ctx.trace_batch(cams, grids, [S.NU_230], opts, images=images, flux=flux)[2]
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(step())
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt * 1e3 / args.steps
-    ray_steps = sum(s.ray_steps for s in stats) / args.steps
-    samples = sum(s.samples for s in stats) / args.steps
-    kern_ms = sum(s.kernel_ms for s in stats) / args.steps
+    plain = time_form(ctx, R, cams, grids, nu, R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=launch),
+                      images, flux, args.steps, args.warmup)
+    ms = plain["ms"]
     w = R.work_per_unit()
-    fp64_flops = ray_steps * w["step_flops"] + samples * w["sample_flops"]
+    fp64_flops = plain["ray_steps"] * w["step_flops"] + plain["samples"] * w["sample_flops"]
     if args.prec == "f64":
-        fp64_flops += samples * w["freq_flops"]
-    achieved = fp64_flops / (kern_ms * 1e-3) / 1e12
+        fp64_flops += plain["samples"] * w["freq_flops"]
+    achieved = fp64_flops / (plain["kernel_ms"] * 1e-3) / 1e12
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        if tj.get("prec") == args.prec and tj.get("res") == args.res:
+        if tj.get("prec") == args.prec and tj.get("res") == args.res and tj.get("kernel_build") == R.kernel_build_id():
             traffic = tj.get("bytes_per_launch")
     out = {
         "metric": "ray-steps/sec and 512^2 images/sec, plain vs MLP-emissivity at <=1e-3 flux err",
-        "value": ray_steps / (ms * 1e-3),
+        "value": plain["ray_steps"] / (ms * 1e-3),
         "unit": "ray-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -135,20 +158,37 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"9 images {args.res}x{args.res} (a in {{0,0.5,0.9375}} x i in {{30,60,85}} deg), "
                                f"r_cam 1e4 M, FOV +-20 M, 230 GHz, float32 256^2 MKS grids, RK4 eps 0.05, "
-                               f"FP64 geodesic + {args.prec.upper()} transfer, exact closure",
+                               f"FP64 geodesic + {args.prec.upper()} transfer, exact closure, {args.launch} launch",
                    "closure": "exact", "images_per_step": len(cams), "rays_per_step": n_pix},
         "images_per_s": len(cams) / (ms * 1e-3),
         "images_512_per_s": len(cams) * (args.res * args.res) / (512 * 512) / (ms * 1e-3),
-        "ray_steps_per_step": ray_steps,
-        "samples_per_step": samples,
-        "kernel_ms": kern_ms,
+        "ray_steps_per_step": plain["ray_steps"],
+        "samples_per_step": plain["samples"],
+        "kernel_ms": plain["kernel_ms"],
+        "kernel_ms_median": plain["kernel_ms_median"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "trace_kernel (fused RK4 geodesic + transfer)",
                      "flops_per_ray_step": w["step_flops"], "flops_per_sample": w["sample_flops"]},
     }
+    if not args.no_mlp:
+        R.mlp_init(ctx)
+        rep = R.mlp_train(ctx)
+        mlp = time_form(ctx, R, cams, grids, nu,
+                        R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=launch, closure=R.CLOSURE_MLP),
+                        images, flux, args.steps, args.warmup)
+        rel = mlp["flux"] / plain["flux"] - 1.0
+        out["mlp"] = {"value": mlp["ray_steps"] / (mlp["ms"] * 1e-3), "unit": "ray-steps/s",
+                      "ms_per_step": mlp["ms"], "kernel_ms": mlp["kernel_ms"],
+                      "images_512_per_s": len(cams) * (args.res * args.res) / (512 * 512) / (mlp["ms"] * 1e-3),
+                      "max_abs_flux_rel_err": float(np.abs(rel).max()),
+                      "flux_rel_err_per_image": [float(x) for x in rel],
+                      "exact_fallback_fraction": mlp["fallback"] / max(mlp["samples"], 1.0),
+                      "form": "split BF16 MFMA, FP32 accumulate",
+                      "training": {"steps": rep.steps, "train_ms": rep.train_ms,
+                                   "val_rms_ln_j": rep.val_rms[0], "val_rms_ln_alpha": rep.val_rms[1]}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sets, opts)
+        out["cpu_baseline"] = cpu_baseline(sets, R.default_opts(transfer_prec=prec))
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -106,12 +106,19 @@ typedef struct {
  * r < r_stop_factor * r_+; max_steps: step limit per ray; transfer_prec: RAPTOR_F64 or
  * RAPTOR_F32 for the emission, absorption and intensity arithmetic (the geodesic is always
  * FP64); closure: RAPTOR_CLOSURE_*; slow_light: 1 to interpolate snapshots along each ray;
- * mem: RAPTOR_MEM_HOST or RAPTOR_MEM_DEVICE for output buffers; mass_msun and dist_pc set
- * the length unit GM/c^2 and the flux distance; metric_mass is 1 (or 0 for flat space, which
- * needs spin 0). */
+ * mem: RAPTOR_MEM_HOST or RAPTOR_MEM_DEVICE for output buffers; launch: 0 or
+ * RAPTOR_LAUNCH_GRAPH; mass_msun and dist_pc set the length unit GM/c^2 and the flux
+ * distance; metric_mass is 1 (or 0 for flat space, which needs spin 0).
+ *
+ * RAPTOR_LAUNCH_GRAPH: the call's device work (counter reset, the persistent trace kernel
+ * and the flux reduction) is captured once into a HIP graph and replayed by later calls
+ * whose launch is identical (same job-table shape, buffers and plan); the job table and
+ * frequencies are uploaded before each replay.  Results are identical to the direct launch;
+ * kernel_ms then spans the whole graph. */
+enum { RAPTOR_LAUNCH_DIRECT = 0, RAPTOR_LAUNCH_GRAPH = 1 };
 typedef struct {
     double eps, r_stop_factor;
-    int32_t max_steps, transfer_prec, closure, slow_light, mem, reserved;
+    int32_t max_steps, transfer_prec, closure, slow_light, mem, launch;
     double mass_msun, dist_pc, const_j, const_alpha, metric_mass;
 } raptor_opts;
 
@@ -188,11 +195,15 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
 /* ------------------------------------------------------------------------------------------
  * Learned closure (an addition to the paper's method).  A 3 -> 64 -> 64 -> 64 -> 64 -> 2 SiLU
  * network maps (ln(nu/nu_c), ln Theta_e, cos theta_B), normalised to [-1, 1] over the box
- * nu/nu_c in [1e-2, 1e6], Theta_e in [0.1, 100], |cos theta_B| <= 0.999, to standardised
+ * nu/nu_c in [1e-2, 1e6], Theta_e in [0.1, 100], |cos theta_B| <= 0.999, to
  * ln j_hat = ln(j / (n_e nu_c J0)) and ln alpha_hat = ln j_hat - 2 ln(nu/nu_c) - ln Theta_e,
  * J0 = sqrt2 pi e^2 / (3c), where alpha_hat is the Rayleigh-Jeans absorption in units of
- * n_e J0 / (2 m_e nu_c); the exact Planck factor is applied when the network is used
- * (closure RAPTOR_CLOSURE_MLP), and the exact closure of Sec. 4.2.2 is used outside the box.
+ * n_e J0 / (2 m_e nu_c).  The network's two outputs are the standardised values of
+ * ln j_hat + X^1/3 and ln alpha_hat + X^1/3, X = nu / nu_s, nu_s = (2/9) nu_c Theta_e^2
+ * sin theta_B: the exponential cut-off exp(-X^1/3) of the emissivity is computed from the
+ * inputs and applied outside the network.  The exact Planck factor is applied when the
+ * network is used (closure RAPTOR_CLOSURE_MLP), and the exact closure of Sec. 4.2.2 is used
+ * outside the box.
  * Training samples are the exact closure, evaluated on the device.  Parameters: for each
  * layer W[out][in] then b[out], 12866 floats.
  * ------------------------------------------------------------------------------------------ */
@@ -204,7 +215,7 @@ enum { RAPTOR_MLP_PARAMS = 12866 };
 typedef struct {
     int64_t n_train;             /* training samples generated on the device (default 1e7) */
     int64_t n_val;               /* validation samples (default 1e5) */
-    int32_t epochs;              /* passes over the training samples (default 6) */
+    int32_t epochs;              /* passes over the training samples (default 60) */
     int32_t batch;               /* samples per Adam step, a multiple of 64 (default 4096) */
     float lr, lr_final;          /* Adam step size, cosine-decayed from lr to lr_final */
     float beta1, beta2, adam_eps, weight_decay;
@@ -243,8 +254,8 @@ raptor_status raptor_mlp_forward(raptor_ctx* ctx, int32_t form, const float* x, 
 raptor_status raptor_mlp_backward(raptor_ctx* ctx, int32_t form, const float* x, const float* dy, int64_t n,
                                   float* dparams);
 /* For raw closure inputs raw[n][3] = (ln(nu/nu_c), ln Theta_e, cos theta_B): the network's
- * (ln j_hat, ln alpha_hat) de-standardised (net, may be NULL) and the exact closure's (exact,
- * may be NULL), [n][2] each. */
+ * (ln j_hat, ln alpha_hat), de-standardised and with the cut-off exponent X^1/3 subtracted
+ * (net, may be NULL), and the exact closure's (exact, may be NULL), [n][2] each. */
 raptor_status raptor_mlp_closure(raptor_ctx* ctx, int32_t form, const float* raw, int64_t n, float* net,
                                  float* exact);
 

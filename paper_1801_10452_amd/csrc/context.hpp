@@ -86,14 +86,18 @@ struct raptor_ctx {
     std::string err;
     rctx::DevBuf<DevJob> jobs;
     rctx::DevBuf<DevGrid> grids;
-    rctx::DevBuf<double> nu, out, pixsr, flux;
+    rctx::DevBuf<double> nu, out, pixsr, flux, flux_part;
     rctx::DevBuf<int> status, steps;
     rctx::DevBuf<unsigned int> counter;
     rctx::DevBuf<unsigned long long> stats;
     rctx::DevBuf<double2> k2;
-    rctx::DevBuf<float2> k2f;
     K2Table k2t{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // graph replay of the batch launch: a capture-only stream, the instantiated graph and the
+    // launch it was captured for (compared bytewise)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::vector<unsigned char> graph_key;
     std::vector<raptor_grid*> live;
     std::map<int, rctx::LaunchPlan> plans;   // key: frequency-count class * 2 + fp32
     rctx::MlpState mlp;

@@ -30,7 +30,6 @@ struct DevJob {
 // ln K2(1/Theta) and its derivative in u = ln Theta at n uniform nodes u0 + i du.
 struct K2Table {
     const double2* tab;
-    const float2* tabf;
     int n, pad;
     double u0, du, inv_du;
 };

@@ -51,22 +51,16 @@ raptor_status build_k2_table(raptor_ctx* ctx)
     const double u0 = std::log(1e-2), u1 = std::log(1e4);
     const double du = (u1 - u0) / (n - 1);
     std::vector<double2> h(n);
-    std::vector<float2> hf(n);
     for (int i = 0; i < n; ++i) {
         const double u = u0 + i * du;
         const double x = std::exp(-u);
         const double k1 = std::cyl_bessel_k(1.0, x), k2 = std::cyl_bessel_k(2.0, x);
         h[i].x = std::log(k2);
         h[i].y = x * k1 / k2 + 2.0;
-        hf[i].x = (float)h[i].x;
-        hf[i].y = (float)h[i].y;
     }
     RAPTOR_CK(ctx->k2.reserve(n), "allocating the K2 table");
-    RAPTOR_CK(ctx->k2f.reserve(n), "allocating the K2 table");
     RAPTOR_CK(hipMemcpy(ctx->k2.p, h.data(), n * sizeof(double2), hipMemcpyHostToDevice), "uploading the K2 table");
-    RAPTOR_CK(hipMemcpy(ctx->k2f.p, hf.data(), n * sizeof(float2), hipMemcpyHostToDevice), "uploading the K2 table");
     ctx->k2t.tab = ctx->k2.p;
-    ctx->k2t.tabf = ctx->k2f.p;
     ctx->k2t.n = n;
     ctx->k2t.u0 = u0;
     ctx->k2t.du = du;
@@ -91,6 +85,8 @@ raptor_status check_opts(raptor_ctx* ctx, const raptor_opts* o)
         return fail(ctx, RAPTOR_E_INVALID, "the MLP closure needs parameters (raptor_mlp_init / set / train)");
     if (o->slow_light != 0 && o->slow_light != 1) return fail(ctx, RAPTOR_E_INVALID, "slow_light must be 0 or 1");
     if (o->mem != RAPTOR_MEM_HOST && o->mem != RAPTOR_MEM_DEVICE) return fail(ctx, RAPTOR_E_INVALID, "unknown mem");
+    if (o->launch != RAPTOR_LAUNCH_DIRECT && o->launch != RAPTOR_LAUNCH_GRAPH)
+        return fail(ctx, RAPTOR_E_INVALID, "unknown launch mode");
     if (!finite_pos(o->mass_msun) || !finite_pos(o->dist_pc))
         return fail(ctx, RAPTOR_E_INVALID, "mass_msun and dist_pc must be positive");
     if (o->metric_mass != 0.0 && o->metric_mass != 1.0) return fail(ctx, RAPTOR_E_INVALID, "metric_mass must be 0 or 1");
@@ -154,15 +150,15 @@ int plan_key(int n_nu, bool fp32, bool mlpc)
 raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* pl, bool mlpc = false)
 {
     // the per-wave sample queue lives in LDS: shrink the work-group until it fits
-    while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.threads) > ctx->lds_per_block)
+    while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc) > ctx->lds_per_block)
         pl->p.threads /= 2;
-    if (trace_kernel_lds(max_nu, fp32, pl->p.threads) > ctx->lds_per_block)
+    if (trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc) > ctx->lds_per_block)
         return fail(ctx, RAPTOR_E_UNSUPPORTED, "the sample queue of one wave exceeds the LDS of a work-group");
     int per_cu = pl->p.blocks_per_cu;
     if (per_cu == 0) {
         RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                       &per_cu, trace_kernel_symbol(max_nu, fp32, pl->p.min_waves_per_simd, mlpc), pl->p.threads,
-                      trace_kernel_lds(max_nu, fp32, pl->p.threads)),
+                      trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc)),
                   "querying occupancy");
         per_cu = std::max(per_cu, 1);
     }
@@ -183,6 +179,70 @@ raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, 
     if (s != RAPTOR_OK) return s;
     ctx->plans[key] = pl;
     *out = pl;
+    return RAPTOR_OK;
+}
+
+// The device work of a call as a HIP graph: reset, trace and flux kernels captured on the
+// capture-only stream (nothing runs during capture) and replayed on the context's stream.  The
+// graph is kept while later calls make the identical launch -- same kernel arguments (every
+// buffer pointer and the job count included), frequency class, precision and plan -- and
+// captured again otherwise.  It holds kernel nodes only; the uploads before it are ordinary
+// stream-ordered copies.
+raptor_status launch_graph(raptor_ctx* ctx, const TraceParams& p, int n_nu, bool fp32, const LaunchPlan& plan, int nj,
+                           double* out)
+{
+    struct Key {
+        TraceParams p;
+        int n_nu, fp32, wpe, blocks, threads, nj;
+        const double* out;
+        const double* pixsr;
+        double* flux;
+        double* flux_part;
+    } k;
+    std::memset(&k, 0, sizeof k);
+    k.p = p;
+    k.n_nu = n_nu;
+    k.fp32 = fp32;
+    k.wpe = plan.p.min_waves_per_simd;
+    k.blocks = plan.blocks;
+    k.threads = plan.p.threads;
+    k.nj = nj;
+    k.out = out;
+    k.pixsr = ctx->pixsr.p;
+    k.flux = ctx->flux.p;
+    k.flux_part = ctx->flux_part.p;
+    const unsigned char* kb = reinterpret_cast<const unsigned char*>(&k);
+    const bool same = ctx->graph && ctx->graph_key.size() == sizeof k &&
+                      std::memcmp(ctx->graph_key.data(), kb, sizeof k) == 0;
+    if (!same) {
+        if (ctx->graph) {
+            RAPTOR_CK(hipGraphExecDestroy(ctx->graph), "releasing the previous graph");
+            ctx->graph = nullptr;
+        }
+        ctx->graph_key.clear();
+        hipStream_t cs = ctx->cap_stream;
+        RAPTOR_CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "starting graph capture");
+        hipError_t e = launch_reset(ctx->counter.p, ctx->stats.p, cs);
+        if (e == hipSuccess) e = launch_trace(p, n_nu, fp32, plan.p.min_waves_per_simd, plan.blocks, plan.p.threads, cs);
+        if (e == hipSuccess) e = launch_flux(ctx->jobs.p, nj, out, ctx->pixsr.p, ctx->flux_part.p, ctx->flux.p, n_nu, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);   // always end the capture
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return dev_fail(ctx, e, "capturing the launch");
+        }
+        RAPTOR_CK(e2, "ending graph capture");
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        RAPTOR_CK(e, "instantiating the graph");
+        ctx->graph = ge;
+        ctx->graph_key.assign(kb, kb + sizeof k);
+    }
+    hipStream_t s = ctx->stream;
+    RAPTOR_CK(hipEventRecord(ctx->ev0, s), "recording an event");
+    RAPTOR_CK(hipGraphLaunch(ctx->graph, s), "launching the graph");
+    RAPTOR_CK(hipEventRecord(ctx->ev1, s), "recording an event");
     return RAPTOR_OK;
 }
 
@@ -258,6 +318,7 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     RAPTOR_CK(ctx->nu.reserve(nus.size()), "allocating frequencies");
     RAPTOR_CK(ctx->pixsr.reserve(nj), "allocating solid angles");
     RAPTOR_CK(ctx->flux.reserve((size_t)nj * n_nu), "allocating fluxes");
+    RAPTOR_CK(ctx->flux_part.reserve(flux_partials(nj, n_nu)), "allocating flux partial sums");
     double* out = nullptr;
     if (dev && images) {
         out = images;
@@ -287,7 +348,8 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     RAPTOR_CK(hipMemcpyAsync(ctx->pixsr.p, pixsr.data(), nj * sizeof(double), hipMemcpyHostToDevice, s),
               "uploading solid angles");
 
-    TraceParams p{};
+    TraceParams p;
+    std::memset(&p, 0, sizeof p);   // padding included: the graph key compares the bytes
     p.jobs = ctx->jobs.p;
     p.grids = ctx->grids.p;
     p.nu = ctx->nu.p;
@@ -313,12 +375,18 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     p.refill_threshold = plan.p.refill_threshold;
     p.tile_shift = tile_w == 8 ? 3 : tile_w == 16 ? 4 : tile_w == 32 ? 5 : 6;
 
-    RAPTOR_CK(launch_reset(ctx->counter.p, ctx->stats.p, s), "launching reset");
-    RAPTOR_CK(hipEventRecord(ctx->ev0, s), "recording an event");
-    RAPTOR_CK(launch_trace(p, n_nu, fp32, plan.p.min_waves_per_simd, plan.blocks, plan.p.threads, s),
-              "launching the trace kernel");
-    RAPTOR_CK(hipEventRecord(ctx->ev1, s), "recording an event");
-    RAPTOR_CK(launch_flux(ctx->jobs.p, nj, out, ctx->pixsr.p, ctx->flux.p, n_nu, s), "launching the flux reduction");
+    if (o->launch == RAPTOR_LAUNCH_GRAPH) {
+        raptor_status gs = launch_graph(ctx, p, n_nu, fp32, plan, nj, out);
+        if (gs != RAPTOR_OK) return gs;
+    } else {
+        RAPTOR_CK(launch_reset(ctx->counter.p, ctx->stats.p, s), "launching reset");
+        RAPTOR_CK(hipEventRecord(ctx->ev0, s), "recording an event");
+        RAPTOR_CK(launch_trace(p, n_nu, fp32, plan.p.min_waves_per_simd, plan.blocks, plan.p.threads, s),
+                  "launching the trace kernel");
+        RAPTOR_CK(hipEventRecord(ctx->ev1, s), "recording an event");
+        RAPTOR_CK(launch_flux(ctx->jobs.p, nj, out, ctx->pixsr.p, ctx->flux_part.p, ctx->flux.p, n_nu, s),
+                  "launching the flux reduction");
+    }
 
     const hipMemcpyKind d2x = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (images && out != images)
@@ -403,6 +471,8 @@ raptor_status raptor_create(int device, void* hip_stream, raptor_ctx** out)
     ctx->lds_per_block = prop.sharedMemPerBlock;
     if ((e = hipEventCreate(&ctx->ev0)) != hipSuccess || (e = hipEventCreate(&ctx->ev1)) != hipSuccess)
         return bail(dev_fail(ctx, e, "creating events"));
+    e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(dev_fail(ctx, e, "creating the capture stream"));
     if ((e = ctx->counter.reserve(1)) != hipSuccess || (e = ctx->stats.reserve(ST_COUNT)) != hipSuccess)
         return bail(dev_fail(ctx, e, "allocating counters"));
     raptor_status s = build_k2_table(ctx);
@@ -424,6 +494,7 @@ void raptor_destroy(raptor_ctx* ctx)
     ctx->jobs.release();
     ctx->grids.release();
     ctx->nu.release();
+    ctx->flux_part.release();
     ctx->out.release();
     ctx->pixsr.release();
     ctx->flux.release();
@@ -432,10 +503,11 @@ void raptor_destroy(raptor_ctx* ctx)
     ctx->counter.release();
     ctx->stats.release();
     ctx->k2.release();
-    ctx->k2f.release();
     ctx->mlp.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -723,7 +795,7 @@ raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer
               "reading kernel attributes");
     RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                   &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd), plan->threads,
-                  trace_kernel_lds(n_nu, fp32, plan->threads)),
+                  trace_kernel_lds(n_nu, fp32, plan->threads, false)),
               "querying occupancy");
     if (vgprs) *vgprs = regs;
     if (scratch_bytes) *scratch_bytes = spill;

@@ -8,14 +8,16 @@ hipError_t launch_reset(unsigned int* tile_counter, unsigned long long* stats, h
 // 512, 256, 168)
 hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, int blocks, int threads,
                         hipStream_t st);
-hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* flux,
-                       int max_nu, hipStream_t st);
+// flux in two deterministic passes through flux_partials(n_jobs, max_nu) partial sums
+size_t flux_partials(int n_jobs, int max_nu);
+hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* part,
+                       double* flux, int max_nu, hipStream_t st);
 hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int* vgprs, int* spill_bytes,
                                    int* max_threads);
 // mlpc: the variant with the learned closure (always the uncapped register variant)
 const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = false);
-// dynamic LDS bytes of a trace-kernel work-group of `threads` lanes
-size_t trace_kernel_lds(int max_nu, bool fp32, int threads);
+// dynamic LDS bytes of a trace-kernel work-group of `threads` lanes (mlpc: plus the staged network)
+size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc);
 
 // ---- learned closure (mlp.hip)
 namespace mlp {

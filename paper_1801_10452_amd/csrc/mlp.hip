@@ -30,19 +30,21 @@ __device__ inline double uniform01(unsigned long long seed, unsigned long long n
 
 }  // namespace
 
-// ln j_hat and ln alpha_hat of the exact closure for raw inputs (ln x, ln Theta, cos), x = nu/nu_c:
+// Exact closure for raw inputs (ln x, ln Theta, cos), x = nu/nu_c, in the log domain:
 // j / (n_e nu_c J0) = (nu_s/nu_c) / K2(1/Theta) t (t + 2^11/12)^2 exp(-t), t = (x nu_c/nu_s)^1/3,
-// nu_s/nu_c = (2/9) Theta^2 sin(theta_B); alpha_hat = j_hat / (x^2 Theta).
-__device__ inline void exact_targets(const K2Table& k2, double lx, double lth, double cb, double* t0, double* t1)
+// nu_s/nu_c = (2/9) Theta^2 sin(theta_B); alpha_hat = j_hat / (x^2 Theta).  Returns the network
+// targets y0 = ln j_hat + t, y1 = ln alpha_hat + t, and t.
+__device__ inline void exact_targets(const K2Table& k2, double lx, double lth, double cb, double* y0, double* y1,
+                                     double* tc)
 {
     const double th = ::exp(lth);
     const double sb = ::sqrt(::fmax(1.0 - cb * cb, 0.0));
     const double ns = (2.0 / 9.0) * th * th * sb;
     const double t = ::cbrt(::exp(lx) / ns);
-    double lj = ::log(ns) - pl::ln_k2(k2, lth) + ::log(t) + 2.0 * ::log(t + pl::TWO_11_12) - t;
-    lj = ::fmax(lj, LNJ_FLOOR);
-    *t0 = lj;
-    *t1 = lj - 2.0 * lx - lth;
+    const double y = ::log(ns) - pl::ln_k2(k2, lth) + ::log(t) + 2.0 * ::log(t + pl::TWO_11_12);
+    *y0 = y;
+    *y1 = y - 2.0 * lx - lth;
+    *tc = t;
 }
 
 __global__ void gen_kernel(K2Table k2, unsigned long long seed, long long n, float* X, float* T, float* raw)
@@ -53,8 +55,8 @@ __global__ void gen_kernel(K2Table k2, unsigned long long seed, long long n, flo
     const double lx = (double)LX_LO + u0 * ((double)LX_HI - (double)LX_LO);
     const double lth = (double)LT_LO + u1 * ((double)LT_HI - (double)LT_LO);
     const double cb = -0.999 + 1.998 * u2;
-    double t0, t1;
-    exact_targets(k2, lx, lth, cb, &t0, &t1);
+    double t0, t1, tc;
+    exact_targets(k2, lx, lth, cb, &t0, &t1, &tc);
     X[3 * i] = norm_lx((float)lx);
     X[3 * i + 1] = norm_lt((float)lth);
     X[3 * i + 2] = norm_cb((float)cb);
@@ -67,15 +69,15 @@ __global__ void gen_kernel(K2Table k2, unsigned long long seed, long long n, flo
     }
 }
 
-// exact targets for given raw inputs (accuracy checks)
+// exact ln j_hat and ln alpha_hat for given raw inputs (accuracy checks)
 __global__ void exact_kernel(K2Table k2, long long n, const float* raw, float* out)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double t0, t1;
-    exact_targets(k2, raw[3 * i], raw[3 * i + 1], raw[3 * i + 2], &t0, &t1);
-    out[2 * i] = (float)t0;
-    out[2 * i + 1] = (float)t1;
+    double t0, t1, tc;
+    exact_targets(k2, raw[3 * i], raw[3 * i + 1], raw[3 * i + 2], &t0, &t1, &tc);
+    out[2 * i] = (float)(t0 - tc);
+    out[2 * i + 1] = (float)(t1 - tc);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -2,13 +2,16 @@
 // BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k) with FP32 accumulation.
 //
 // Inputs (normalised to [-1, 1] over the training box): ln(nu/nu_c), ln Theta_e, cos theta_B.
-// Outputs (standardised): ln j_hat and ln alpha_hat, where, with J0 = sqrt2 pi e^2 / (3 c),
+// Outputs: ln j_hat and ln alpha_hat, where, with J0 = sqrt2 pi e^2 / (3 c),
 //     j = n_e nu_c J0 exp(ln j_hat)                          (emission, Sec. 4.2.2)
 //     alpha_RJ = n_e J0 / (2 m_e nu_c) exp(ln alpha_hat)    (Kirchhoff absorption with the
 //                                                            Rayleigh-Jeans Planck function)
 // and alpha = alpha_RJ expm1(y)/y, y = h nu / (m_e c^2 Theta_e), restores the exact Planck
-// function.  Targets below ln j_hat = -40 (emission weaker than e^-40 of typical values) are
-// clipped to -40.
+// function.  The exponential cut-off of thermal synchrotron emission, exp(-X^1/3) with
+// X = nu/nu_s and nu_s/nu_c = (2/9) Theta_e^2 sin theta_B, is factored out of both outputs:
+// the network predicts the standardised values of ln j_hat + X^1/3 and ln alpha_hat + X^1/3
+// (smooth, ranges about [-7, 25] and [-28, 19] over the box, where ln j_hat itself falls to
+// about -1800), and the caller subtracts X^1/3, which it computes from the inputs.
 //
 // Precision.  Weights are stored as BF16 pairs (hi = bf16(w), lo = bf16(w - hi)); the forward
 // pass forms hi.hi + hi.lo + lo.hi products (three MFMAs, FP32 accumulate, about 16 mantissa
@@ -38,8 +41,7 @@ constexpr int PW1 = 0, PW2 = 1024, PW3 = 5120, PW4 = 9216, PW5 = 13312, PW_TOTAL
 constexpr float LX_LO = -4.605170185988091f, LX_HI = 13.815510557964274f;
 constexpr float LT_LO = -2.302585092994046f, LT_HI = 4.605170185988092f;
 constexpr float CB_LO = -0.999f, CB_HI = 0.999f;
-constexpr float MU_J = -10.0f, SIGMA_J = 14.0f, MU_A = -20.0f, SIGMA_A = 22.0f;
-constexpr double LNJ_FLOOR = -40.0;
+constexpr float MU_J = 4.0f, SIGMA_J = 6.0f, MU_A = -6.5f, SIGMA_A = 9.0f;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -138,44 +140,123 @@ struct Net {
     const unsigned short *W, *Wlo, *WT;
 };
 
+// The 56 A-fragments of a forward pass: layer 1 (m-tiles 0..3), layers 2..4 (m-tile, k-tile),
+// output layer (k-tiles 0..3).
+constexpr int N_FRAGS = 56;
+__host__ __device__ constexpr int frag_index(int layer, int mt, int kt)
+{
+    return layer == 0 ? mt : layer < 4 ? 4 + 16 * (layer - 1) + 4 * mt + kt : 52 + kt;
+}
+// offset of the bias of hidden layer L (0..3) in the FP32 parameters
+__host__ __device__ constexpr int hidden_bias_off(int L) { return OFF_B1 + (OFF_B2 - OFF_B1) * L; }
+static_assert(hidden_bias_off(2) == OFF_B3 && hidden_bias_off(3) == OFF_B4, "parameter layout");
+
+// Weight source: global memory, row-major padded BF16 (read per fragment through the caches).
+template <bool SPLIT>
+struct GlobalWeights {
+    const Net& net;
+    __device__ inline Split w(int layer, int mt, int kt, int lane) const
+    {
+        const int pw[5] = {PW1, PW2, PW3, PW4, PW5};
+        const int stride = layer == 0 ? 16 : 64;
+        return frag_w<SPLIT>(net.W + pw[layer], net.Wlo + pw[layer], stride, 16 * mt, 16 * kt, lane);
+    }
+    __device__ inline const float* bias(int layer) const { return net.P + hidden_bias_off(layer); }
+    __device__ inline float out_bias(int o) const { return net.P[OFF_B5 + o]; }
+};
+
+// Weight source: a work-group's LDS copy in fragment order -- fragment f of lane l is the
+// 16-byte pair {hi, lo} at (64 f + l) * 16, so a lane's fragment is one conflict-free 128-bit
+// LDS read -- followed by the hidden biases [4][64] and the two output biases.
+constexpr int LDS_FRAG_BYTES = N_FRAGS * 64 * 16;
+constexpr int LDS_NET_BYTES = LDS_FRAG_BYTES + (4 * 64 + 4) * 4;
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+template <bool SPLIT>
+struct LdsWeights {
+    const bf16x8* frag;
+    const float* b;
+    __device__ inline Split w(int layer, int mt, int kt, int lane) const
+    {
+        const bf16x8 v = frag[64 * frag_index(layer, mt, kt) + lane];
+        Split s;
+        s.hi = __builtin_shufflevector(v, v, 0, 1, 2, 3);
+        s.lo = SPLIT ? __builtin_shufflevector(v, v, 4, 5, 6, 7) : bf16x4{0, 0, 0, 0};
+        return s;
+    }
+    __device__ inline const float* bias(int layer) const { return b + 64 * layer; }
+    __device__ inline float out_bias(int o) const { return b[256 + o]; }
+};
+
+// Copy the network into LDS in the LdsWeights layout (all threads of the work-group take part;
+// the caller synchronises the work-group afterwards).
+__device__ inline void stage_weights(const Net& net, unsigned char* lds, int tid, int nthreads)
+{
+    bf16x4* fr = reinterpret_cast<bf16x4*>(lds);
+    for (int s = tid; s < N_FRAGS * 64; s += nthreads) {
+        const int f = s >> 6, lane = s & 63;
+        int pw, stride = 64, m0 = 0, k0 = 0;
+        if (f < 4) {
+            pw = PW1;
+            stride = 16;
+            m0 = 16 * f;
+        } else if (f < 52) {
+            const int L = (f - 4) >> 4, r = (f - 4) & 15;
+            pw = L == 0 ? PW2 : L == 1 ? PW3 : PW4;
+            m0 = 16 * (r >> 2);
+            k0 = 16 * (r & 3);
+        } else {
+            pw = PW5;
+            k0 = 16 * (f - 52);
+        }
+        fr[2 * s] = frag_a(net.W + pw, stride, m0, k0, lane);
+        fr[2 * s + 1] = frag_a(net.Wlo + pw, stride, m0, k0, lane);
+    }
+    float* b = reinterpret_cast<float*>(lds + LDS_FRAG_BYTES);
+    for (int i = tid; i < 4 * 64 + 4; i += nthreads)
+        b[i] = i < 256 ? net.P[hidden_bias_off(i >> 6) + (i & 63)] : (i < 258 ? net.P[OFF_B5 + i - 256] : 0.0f);
+}
+
 // Forward pass of one 16-sample column block.  bx: input B fragment (lanes 0..15 hold the
 // three inputs of sample n = lane, the other lanes zeros).  Returns the output fragment: lanes
 // 0..15 hold (y0, y1) of their sample in .x, .y (bias included).  z (optional) receives the
 // pre-activations of the four hidden layers, z[4 * L + mt].
-template <bool SPLIT>
-__device__ inline f32x4 forward_block(const Net& net, const Split& bx, int lane, f32x4* z = nullptr)
+template <bool SPLIT, class WS>
+__device__ inline f32x4 forward_block(const WS& ws, const Split& bx, int lane, f32x4* z = nullptr)
 {
     const int g4 = 4 * (lane >> 4);
     Split h[4];
     f32x4 acc[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-        acc[mt] = mfma_s<SPLIT>(frag_w<SPLIT>(net.W + PW1, net.Wlo + PW1, 16, 16 * mt, 0, lane), bx, f32x4{0, 0, 0, 0});
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = mfma_s<SPLIT>(ws.w(0, mt, 0, lane), bx, f32x4{0, 0, 0, 0});
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) h[mt] = activate<SPLIT>(acc[mt], net.P + OFF_B1 + 16 * mt + g4, z ? &z[mt] : nullptr);
-    const int pw[3] = {PW2, PW3, PW4};
-    const int pb[3] = {OFF_B2, OFF_B3, OFF_B4};
+    for (int mt = 0; mt < 4; ++mt) h[mt] = activate<SPLIT>(acc[mt], ws.bias(0) + 16 * mt + g4, z ? &z[mt] : nullptr);
 #pragma unroll
-    for (int L = 0; L < 3; ++L) {
+    for (int L = 1; L < 4; ++L) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             f32x4 a = f32x4{0, 0, 0, 0};
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt)
-                a = mfma_s<SPLIT>(frag_w<SPLIT>(net.W + pw[L], net.Wlo + pw[L], 64, 16 * mt, 16 * kt, lane), h[kt], a);
+            for (int kt = 0; kt < 4; ++kt) a = mfma_s<SPLIT>(ws.w(L, mt, kt, lane), h[kt], a);
             acc[mt] = a;
         }
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-            h[mt] = activate<SPLIT>(acc[mt], net.P + pb[L] + 16 * mt + g4, z ? &z[4 * (L + 1) + mt] : nullptr);
+            h[mt] = activate<SPLIT>(acc[mt], ws.bias(L) + 16 * mt + g4, z ? &z[4 * L + mt] : nullptr);
     }
     f32x4 o = f32x4{0, 0, 0, 0};
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt)
-        o = mfma_s<SPLIT>(frag_w<SPLIT>(net.W + PW5, net.Wlo + PW5, 64, 0, 16 * kt, lane), h[kt], o);
-    o.x += net.P[OFF_B5];
-    o.y += net.P[OFF_B5 + 1];
+    for (int kt = 0; kt < 4; ++kt) o = mfma_s<SPLIT>(ws.w(4, 0, kt, lane), h[kt], o);
+    o.x += ws.out_bias(0);
+    o.y += ws.out_bias(1);
     return o;
+}
+
+template <bool SPLIT>
+__device__ inline f32x4 forward_block(const Net& net, const Split& bx, int lane, f32x4* z = nullptr)
+{
+    return forward_block<SPLIT>(GlobalWeights<SPLIT>{net}, bx, lane, z);
 }
 
 // Input fragment of column block cb from per-lane inputs (one sample per lane).
@@ -201,15 +282,15 @@ __device__ inline Split input_block(float x0, float x1, float x2, int cb, int la
 
 // Forward pass of 64 samples, one per lane (all 64 lanes must call it together).  x0..x2 are
 // this lane's normalised inputs; returns this lane's standardised outputs.
-template <bool SPLIT>
-__device__ inline void forward_wave(const Net& net, float x0, float x1, float x2, float* y0, float* y1)
+template <bool SPLIT, class WS>
+__device__ inline void forward_wave(const WS& ws, float x0, float x1, float x2, float* y0, float* y1)
 {
     const int lane = threadIdx.x & 63;
     float r0 = 0.0f, r1 = 0.0f;
 #pragma unroll 1
     for (int cb = 0; cb < 4; ++cb) {
         const Split bx = input_block<SPLIT>(x0, x1, x2, cb, lane);
-        const f32x4 o = forward_block<SPLIT>(net, bx, lane);
+        const f32x4 o = forward_block<SPLIT>(ws, bx, lane);
         const float v0 = __shfl(o.x, lane & 15, 64), v1 = __shfl(o.y, lane & 15, 64);
         if ((lane >> 4) == cb) {
             r0 = v0;
@@ -224,6 +305,14 @@ __device__ inline void forward_wave(const Net& net, float x0, float x1, float x2
 __host__ __device__ inline float norm_lx(float v) { return 2.0f * (v - LX_LO) / (LX_HI - LX_LO) - 1.0f; }
 __host__ __device__ inline float norm_lt(float v) { return 2.0f * (v - LT_LO) / (LT_HI - LT_LO) - 1.0f; }
 __host__ __device__ inline float norm_cb(float v) { return 2.0f * (v - CB_LO) / (CB_HI - CB_LO) - 1.0f; }
+// The cut-off exponent X^1/3 of the raw inputs (x = nu/nu_c, Theta_e, cos theta_B).
+__host__ __device__ inline double cutoff_exponent(double lx, double lth, double cb)
+{
+    const double sb2 = 1.0 - cb * cb;
+    const double nus_over_nuc = (2.0 / 9.0) * ::exp(2.0 * lth) * ::sqrt(sb2 > 0.0 ? sb2 : 0.0);
+    return ::cbrt(::exp(lx) / nus_over_nuc);
+}
+
 __host__ __device__ inline bool in_box(float lx, float lth, float cb)
 {
     return lx >= LX_LO && lx <= LX_HI && lth >= LT_LO && lth <= LT_HI && cb >= CB_LO && cb <= CB_HI;

@@ -113,9 +113,9 @@ raptor_status raptor_mlp_default_cfg(raptor_mlp_train_cfg* c)
     std::memset(c, 0, sizeof *c);
     c->n_train = 10000000;
     c->n_val = 100000;
-    c->epochs = 6;
+    c->epochs = 60;
     c->batch = 4096;
-    c->lr = 2e-3f;
+    c->lr = 3e-3f;
     c->lr_final = 2e-5f;
     c->beta1 = 0.9f;
     c->beta2 = 0.999f;
@@ -283,9 +283,11 @@ raptor_status raptor_mlp_train(raptor_ctx* ctx, const raptor_mlp_train_cfg* c, r
         DevBuf<float> Y;
         RAPTOR_CK(Y.reserve((size_t)2 * c->n_val), "allocating validation outputs");
         RAPTOR_CK(mlp_launch_forward(net, c->form == RAPTOR_MLP_SPLIT, S.Xva.p, c->n_val, Y.p, st), "validating");
-        std::vector<float> y((size_t)2 * c->n_val), t((size_t)2 * c->n_val);
+        std::vector<float> y((size_t)2 * c->n_val), t((size_t)2 * c->n_val), raw((size_t)3 * c->n_val);
         RAPTOR_CK(hipMemcpyAsync(y.data(), Y.p, y.size() * 4, hipMemcpyDeviceToHost, st), "reading validation");
         RAPTOR_CK(hipMemcpyAsync(t.data(), S.Tva.p, t.size() * 4, hipMemcpyDeviceToHost, st), "reading validation");
+        RAPTOR_CK(hipMemcpyAsync(raw.data(), S.RAWva.p, raw.size() * 4, hipMemcpyDeviceToHost, st),
+                  "reading validation");
         RAPTOR_CK(hipStreamSynchronize(st), "validating");
         Y.release();
         double ss[2] = {0, 0}, mx[2] = {0, 0}, sb = 0.0;
@@ -296,7 +298,9 @@ raptor_status raptor_mlp_train(raptor_ctx* ctx, const raptor_mlp_train_cfg* c, r
                 const double e = (double)(y[2 * i + o] - t[2 * i + o]) * sig[o];
                 ss[o] += e * e;
                 mx[o] = std::max(mx[o], std::fabs(e));
-                if (o == 0 && t[2 * i] * sig[0] + mu[0] > -20.0) {
+                // bright: ln j_hat > -20 (the target is ln j_hat plus the cut-off exponent)
+                if (o == 0 && t[2 * i] * sig[0] + mu[0] -
+                                      mlp::cutoff_exponent(raw[3 * i], raw[3 * i + 1], raw[3 * i + 2]) > -20.0) {
                     sb += e * e;
                     ++nb;
                 }
@@ -407,8 +411,9 @@ raptor_status raptor_mlp_closure(raptor_ctx* ctx, int32_t form, const float* raw
         raptor_status s = raptor_mlp_forward(ctx, form, x.data(), n, y.data());
         if (s != RAPTOR_OK) return s;
         for (int64_t i = 0; i < n; ++i) {
-            net[2 * i] = y[2 * i] * mlp::SIGMA_J + mlp::MU_J;
-            net[2 * i + 1] = y[2 * i + 1] * mlp::SIGMA_A + mlp::MU_A;
+            const double tc = mlp::cutoff_exponent(raw[3 * i], raw[3 * i + 1], raw[3 * i + 2]);
+            net[2 * i] = (float)(y[2 * i] * mlp::SIGMA_J + mlp::MU_J - tc);
+            net[2 * i + 1] = (float)(y[2 * i + 1] * mlp::SIGMA_A + mlp::MU_A - tc);
         }
     }
     return RAPTOR_OK;

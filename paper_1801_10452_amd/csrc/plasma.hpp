@@ -50,21 +50,6 @@ __host__ __device__ inline T mks_x2(T h, T th, T x0)
     return x;
 }
 
-// Float variant of ln_k2 on the float copy of the table.
-__device__ inline float ln_k2f(const K2Table& t, float lnth)
-{
-    float q = (lnth - (float)t.u0) * (float)t.inv_du;
-    q = ::fminf(::fmaxf(q, 0.0f), (float)(t.n - 1) - 1e-3f);
-    const int i = (int)q;
-    const float s = q - i;
-    const float2 A = t.tabf[i], B = t.tabf[i + 1];
-    const float du = (float)t.du;
-    const float s2 = s * s, s3 = s2 * s;
-    const float h00 = 2.0f * s3 - 3.0f * s2 + 1.0f, h10 = s3 - 2.0f * s2 + s;
-    const float h01 = -2.0f * s3 + 3.0f * s2, h11 = s3 - s2;
-    return h00 * A.x + h10 * A.y * du + h01 * B.x + h11 * B.y * du;
-}
-
 // Bilinear combination of the four corner values of each field (weights w1 along x1, w2
 // along x2).
 template <class T>

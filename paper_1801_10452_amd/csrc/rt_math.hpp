@@ -95,6 +95,33 @@ __host__ __device__ inline double rsqrt_nr(double x)
 #endif
 }
 
+// e^x as a float for an argument held in double: x log2(e) = n + f with n = rint and |f| <= 1/2
+// formed in double, then 2^f from the hardware exp2 (about 1 ulp on [-1/2, 1/2]) scaled by 2^n.
+// The relative error stays near one float ulp for any x, where expf((float)x) would lose
+// |x| ulps to the rounding of its argument.  Results below the float range flush to zero.
+__host__ __device__ inline float exp_mixed(double x)
+{
+    const double z = x * 1.4426950408889634;
+    if (z < -160.0) return 0.0f;
+    const double n = __builtin_rint(z < 160.0 ? z : 160.0);
+    const float f = (float)(z - n);
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
+#else
+    return std::ldexp(std::exp2(f), (int)n);
+#endif
+}
+
+// Cube root of a positive double below ~1e38: the float cube root refined by one Newton step
+// in double (t <- t + (x - t^3) / (3 t^2), the quotient's float precision only scaling the
+// already small correction), relative error near 1e-14.
+__host__ __device__ inline double cbrt_refined(double x)
+{
+    const float tf = ::cbrtf((float)x);
+    const double td = (double)tf;
+    return td + (x - td * td * td) * (double)(1.0f / (3.0f * tf * tf));
+}
+
 // ---------------------------------------------------------------- operation counting (host only)
 struct OpTally {
     double flops = 0.0, special = 0.0;

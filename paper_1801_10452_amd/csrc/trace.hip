@@ -71,9 +71,14 @@ struct Transfer<double> {
     }
 };
 
+// FP32 transfer.  The coefficients j, alpha, S, the step's optical depth and contribution are
+// float; the arguments of the exponentials whose size amplifies rounding -- X^1/3 in the
+// emissivity (up to ~40) and ln K2 -- are formed in double and exponentiated by exp_mixed, so
+// every coefficient carries a few float ulps independent of the argument's size.
 template <>
 struct Transfer<float> {
     float ne, the, nu_s, k2_inv, ds, inr3;
+    double nr_inv_nus;   // nu_r / nu_s: X = nu_obs nu_r / nu_s in double
     double nr;
     bool emits;
     __device__ inline void setup(const TraceParams& p, const double fl[4], double nr_, double cosb, double dsv)
@@ -82,15 +87,17 @@ struct Transfer<float> {
         the = (float)fl[1];
         nr = nr_;
         ds = (float)dsv;
-        inr3 = (float)(1.0 / (nr_ * nr_ * nr_));
+        inr3 = (float)rt::rcp_nr(nr_ * nr_ * nr_);
         const double s2 = 1.0 - cosb * cosb;
         const double sb = s2 > 0.0 ? ::sqrt(s2) : 0.0;
         emits = (fl[0] > 0.0 && fl[1] > 0.0 && fl[2] > 0.0 && sb > 0.0);
-        nu_s = (float)((2.0 / 9.0) * pl::NUC_PER_GAUSS * fl[2] * fl[1] * fl[1] * sb);
+        const double nus = (2.0 / 9.0) * pl::NUC_PER_GAUSS * fl[2] * fl[1] * fl[1] * sb;
+        nu_s = (float)nus;
+        nr_inv_nus = emits ? nr_ * rt::rcp_nr(nus) : 0.0;
         k2_inv = 0.0f;
         if (emits && p.closure != CL_CONST)
             k2_inv = (p.closure == CL_K2_PAPER) ? 1.0f / (2.0f * the * the)
-                                               : ::expf(-pl::ln_k2f(p.k2, ::logf(the)));
+                                               : rt::exp_mixed(-pl::ln_k2(p.k2, ::log(fl[1])));
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, float& A, float& dtau) const
     {
@@ -100,11 +107,13 @@ struct Transfer<float> {
             al = (float)p.const_alpha;
             S = al > 0.0f ? j / al : 0.0f;
         } else if (emits) {
-            const float nuf = (float)(nu_obs * nr);
-            const float X = nuf / nu_s;
-            const float t = ::cbrtf(X);
+            const double X = nu_obs * nr_inv_nus;
+            if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
+            const double tt = rt::cbrt_refined(X);
+            const float t = (float)tt;
             const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
-            j = 1.1396857174835936e-29f * ne * nu_s * k2_inv * t * tc * tc * ::expf(-t);
+            j = 1.1396857174835936e-29f * ne * nu_s * k2_inv * t * tc * tc * rt::exp_mixed(-tt);
+            const float nuf = (float)(nu_obs * nr);
             const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
             S = q * q * q / ::expm1f((float)pl::H_OVER_MEC2 * nuf / the);
             al = j / S;
@@ -114,6 +123,14 @@ struct Transfer<float> {
         pl::step_source(j, al, S, ds, inr3, A, dtau);
     }
 };
+
+// Attenuation e^-tau of the accumulated optical depth (held in double in both precisions).
+template <class TT>
+__device__ inline TT attenuation(double tau);
+template <>
+__device__ inline double attenuation<double>(double tau) { return ::exp(-tau); }
+template <>
+__device__ inline float attenuation<float>(double tau) { return rt::exp_mixed(-tau); }
 
 // ---------------------------------------------------------------------------------------
 // Sample compaction.  A lane whose ray takes a step inside the plasma does not evaluate the
@@ -176,8 +193,9 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
 // network evaluations (one per frequency); lanes without a sample feed zeros.  Samples whose
 // closure inputs leave the training box use the exact closure.
 template <int NNU, class TT>
-__device__ inline void eval_round_mlp(const TraceParams& p, bool has, const double* q, const LaneInfo& li, TT* A,
-                                      TT* dtau, unsigned long long& c_zamo, unsigned long long& c_fallback)
+__device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char* lds_net, bool has, const double* q,
+                                      const LaneInfo& li, TT* A, TT* dtau, unsigned long long& c_zamo,
+                                      unsigned long long& c_fallback)
 {
     double fl[4] = {0.0, 1.0, 1.0, 0.0};
     double nr = 1.0, cb = 0.0;
@@ -192,7 +210,8 @@ __device__ inline void eval_round_mlp(const TraceParams& p, bool has, const doub
         tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
     }
     c_zamo += __popcll(__ballot(zamo));
-    const mlp::Net net{p.mlp_P, p.mlp_W, p.mlp_Wlo, nullptr};
+    const mlp::bf16x8* frags = reinterpret_cast<const mlp::bf16x8*>(lds_net);
+    const float* biases = reinterpret_cast<const float*>(lds_net + mlp::LDS_FRAG_BYTES);
     const double nuc = pl::NUC_PER_GAUSS * fl[2];
     const float lth = (float)::log(fl[1] > 0.0 ? fl[1] : 1.0);
     const double ds = nr * q[7] * p.length_unit;
@@ -208,14 +227,17 @@ __device__ inline void eval_round_mlp(const TraceParams& p, bool has, const doub
                     x2 = inb ? mlp::norm_cb((float)cb) : 0.0f;
         float y0, y1;
         if (p.closure == CL_MLP_BF16)
-            mlp::forward_wave<false>(net, x0, x1, x2, &y0, &y1);
+            mlp::forward_wave<false>(mlp::LdsWeights<false>{frags, biases}, x0, x1, x2, &y0, &y1);
         else
-            mlp::forward_wave<true>(net, x0, x1, x2, &y0, &y1);
+            mlp::forward_wave<true>(mlp::LdsWeights<true>{frags, biases}, x0, x1, x2, &y0, &y1);
         if (!act) continue;
         A[f] = TT(0);
         dtau[f] = TT(0);
         if (inb) {
-            const TT lnj = (TT)(y0 * mlp::SIGMA_J + mlp::MU_J), lna = (TT)(y1 * mlp::SIGMA_A + mlp::MU_A);
+            // the network gives ln j_hat + X^1/3 and ln alpha_hat + X^1/3 (standardised)
+            const double sb2 = 1.0 - cb * cb;
+            const double tc = rt::cbrt_refined(nu / ((2.0 / 9.0) * nuc * fl[1] * fl[1] * ::sqrt(sb2)));
+            const TT lnj = (TT)(y0 * mlp::SIGMA_J + mlp::MU_J - tc), lna = (TT)(y1 * mlp::SIGMA_A + mlp::MU_A - tc);
             const TT ne = (TT)fl[0], nucT = (TT)nuc;
             const TT j = ne * nucT * (TT)pl::J_PREF * rt::exp_(lnj);
             const TT yy = (TT)(pl::H_OVER_MEC2 * nu / fl[1]);
@@ -242,15 +264,23 @@ trace_kernel(TraceParams p)
     int* slot_map = reinterpret_cast<int*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES);      // [SLOTS]
     LaneInfo* info = reinterpret_cast<LaneInfo*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES + Q::MAP_BYTES);
     const double M = p.M;
+    // learned closure: the work-group's copy of the network, after the queues of its waves
+    unsigned char* lds_net = smem + (size_t)(blockDim.x >> 6) * Q::PER_WAVE;
+    if (MLPC) {
+        const mlp::Net net{p.mlp_P, p.mlp_W, p.mlp_Wlo, nullptr};
+        mlp::stage_weights(net, lds_net, threadIdx.x, blockDim.x);
+        __syncthreads();
+    }
 
     // ray state of this lane
     double y[8];
     double a = 0.0, r_stop = 0.0, r_esc = 0.0, sth = 0.0, cth = 1.0;
     int job = 0, steps = 0, pix = 0, n_nu = 0, grid = 0, pending = 0;
     bool active = false;
-    TT I[NNU], tau[NNU];
+    // accumulated intensity and optical depth in double (the per-sample terms are TT)
+    double I[NNU], tau[NNU];
 #pragma unroll
-    for (int f = 0; f < NNU; ++f) { I[f] = TT(0); tau[f] = TT(0); }
+    for (int f = 0; f < NNU; ++f) { I[f] = 0.0; tau[f] = 0.0; }
 #pragma unroll
     for (int i = 0; i < 8; ++i) y[i] = 0.0;
 
@@ -306,7 +336,7 @@ trace_kernel(TraceParams p)
                         info[lane] = LaneInfo{a, J.grid, J.fast_snap, J.nu_base, J.n_nu};
                         steps = 0;
 #pragma unroll
-                        for (int f = 0; f < NNU; ++f) { I[f] = TT(0); tau[f] = TT(0); }
+                        for (int f = 0; f < NNU; ++f) { I[f] = 0.0; tau[f] = 0.0; }
                         active = true;
                     }
                 }
@@ -385,7 +415,7 @@ trace_kernel(TraceParams p)
 #pragma unroll
                     for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * Q::SLOTS + s] : 1.0;
                     TT A[NNU], dt[NNU];
-                    eval_round_mlp<NNU, TT>(p, has, q, info[s / K], A, dt, c_zamo, c_fallback);
+                    eval_round_mlp<NNU, TT>(p, lds_net, has, q, info[s / K], A, dt, c_zamo, c_fallback);
                     if (has) {
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
@@ -420,8 +450,8 @@ trace_kernel(TraceParams p)
 #pragma unroll
                     for (int f = 0; f < NNU; ++f) {
                         if (f < n_nu) {
-                            I[f] = I[f] + rt::exp_(-tau[f]) * res[s * 2 * NNU + f];
-                            tau[f] = tau[f] + res[s * 2 * NNU + NNU + f];
+                            I[f] = I[f] + (double)(attenuation<TT>(tau[f]) * res[s * 2 * NNU + f]);
+                            tau[f] = tau[f] + (double)res[s * 2 * NNU + NNU + f];
                         }
                     }
                 }
@@ -437,7 +467,7 @@ trace_kernel(TraceParams p)
             double* o = p.out + J.out_base + pix;
 #pragma unroll
             for (int f = 0; f < NNU; ++f)
-                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : (double)I[f];
+                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : I[f];
             if (p.ray_status) p.ray_status[J.pix_base + pix] = status;
             if (p.ray_steps) p.ray_steps[J.pix_base + pix] = steps;
             active = false;
@@ -462,29 +492,46 @@ trace_kernel(TraceParams p)
     }
 }
 
-// Flux density per (job, frequency): sum of the job's image times the pixel solid angle and
-// 1e23 (erg/s/cm^2/Hz -> Jy).  One block per (job, frequency); every thread sums a fixed
-// strided subset in order and the block combines the partial sums in a fixed tree, so the
-// result does not depend on scheduling.
-__global__ void __launch_bounds__(256) flux_kernel(const DevJob* jobs, const double* out, const double* pix_sr,
-                                                   double* flux, int max_nu)
+// Flux density per (job, frequency): the sum of the job's image times the pixel solid angle
+// and 1e23 (erg/s/cm^2/Hz -> Jy).  Pass 1: FLUX_SPLIT blocks per (job, frequency), block b
+// summing the pixels b * 256 + t + k * 256 * FLUX_SPLIT of every thread t in order and
+// combining its threads in a fixed tree.  Pass 2: one thread per (job, frequency) adds the
+// FLUX_SPLIT partial sums in order.  The result does not depend on scheduling.
+constexpr int FLUX_SPLIT = 16;
+
+__global__ void __launch_bounds__(256) flux_partial_kernel(const DevJob* jobs, const double* out, double* part,
+                                                           int max_nu)
 {
-    const int job = blockIdx.x / max_nu, f = blockIdx.x % max_nu;
+    const int b = blockIdx.x % FLUX_SPLIT;
+    const int jf = blockIdx.x / FLUX_SPLIT;
+    const int job = jf / max_nu, f = jf % max_nu;
     const DevJob& J = jobs[job];
-    __shared__ double part[256];
+    __shared__ double red[256];
     double s = 0.0;
     if (f < J.n_nu) {
         const long long npix = (long long)J.nx * J.ny;
         const double* img = out + J.out_base + f * npix;
-        for (long long i = threadIdx.x; i < npix; i += blockDim.x) s += img[i];
+        for (long long i = (long long)b * 256 + threadIdx.x; i < npix; i += 256ll * FLUX_SPLIT) s += img[i];
     }
-    part[threadIdx.x] = s;
+    red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && f < J.n_nu) flux[job * max_nu + f] = part[0] * pix_sr[job] * 1e23;
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void flux_final_kernel(const DevJob* jobs, const double* part, const double* pix_sr, double* flux,
+                                  int n_jobs, int max_nu)
+{
+    const int jf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (jf >= n_jobs * max_nu) return;
+    const int job = jf / max_nu, f = jf % max_nu;
+    if (f >= jobs[job].n_nu) return;
+    double s = 0.0;
+    for (int b = 0; b < FLUX_SPLIT; ++b) s += part[(size_t)jf * FLUX_SPLIT + b];
+    flux[jf] = s * pix_sr[job] * 1e23;
 }
 
 __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* stats)
@@ -523,17 +570,26 @@ hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, in
 {
     const void* fn = trace_kernel_symbol(max_nu, fp32, wpe, p.closure >= CL_MLP);
     void* args[] = {const_cast<TraceParams*>(&p)};
-    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, trace_kernel_lds(max_nu, fp32, threads), st);
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args,
+                           trace_kernel_lds(max_nu, fp32, threads, p.closure >= CL_MLP), st);
 }
 
-hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* flux,
-                       int max_nu, hipStream_t st)
+size_t flux_partials(int n_jobs, int max_nu) { return (size_t)n_jobs * max_nu * FLUX_SPLIT; }
+
+hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* part,
+                       double* flux, int max_nu, hipStream_t st)
 {
-    hipLaunchKernelGGL(flux_kernel, dim3(n_jobs * max_nu), dim3(256), 0, st, jobs, out, pix_sr, flux, max_nu);
+    hipLaunchKernelGGL(flux_partial_kernel, dim3(n_jobs * max_nu * FLUX_SPLIT), dim3(256), 0, st, jobs, out, part,
+                       max_nu);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = n_jobs * max_nu;
+    hipLaunchKernelGGL(flux_final_kernel, dim3((n + 255) / 256), dim3(256), 0, st, jobs, part, pix_sr, flux, n_jobs,
+                       max_nu);
     return hipGetLastError();
 }
 
-size_t trace_kernel_lds(int max_nu, bool fp32, int threads)
+size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc)
 {
     const int waves = threads / 64;
     auto per = [&](auto tt) -> size_t {
@@ -544,7 +600,7 @@ size_t trace_kernel_lds(int max_nu, bool fp32, int threads)
         if (max_nu <= 16) return Queue<16, TT>::PER_WAVE;
         return Queue<32, TT>::PER_WAVE;
     };
-    return waves * (fp32 ? per(0.0f) : per(0.0));
+    return waves * (fp32 ? per(0.0f) : per(0.0)) + (mlpc ? (size_t)mlp::LDS_NET_BYTES : 0);
 }
 
 const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc)

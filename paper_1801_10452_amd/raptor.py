@@ -19,6 +19,7 @@ F32, F64 = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 CLOSURE_EXACT, CLOSURE_K2_PAPER, CLOSURE_CONST, CLOSURE_MLP, CLOSURE_MLP_BF16 = 0, 1, 2, 3, 4
 MLP_SPLIT, MLP_BF16, MLP_F32 = 0, 1, 2
+LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
 MLP_PARAMS = 12866
 RAY_HORIZON, RAY_ESCAPED, RAY_MAXSTEP, RAY_NUMERIC = 1, 2, 3, 4
 MAX_NU = 32
@@ -48,7 +49,7 @@ class CGridDesc(C.Structure):
 class COpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("r_stop_factor", C.c_double), ("max_steps", C.c_int32),
                 ("transfer_prec", C.c_int32), ("closure", C.c_int32), ("slow_light", C.c_int32), ("mem", C.c_int32),
-                ("reserved", C.c_int32), ("mass_msun", C.c_double), ("dist_pc", C.c_double),
+                ("launch", C.c_int32), ("mass_msun", C.c_double), ("dist_pc", C.c_double),
                 ("const_j", C.c_double), ("const_alpha", C.c_double), ("metric_mass", C.c_double)]
 
 
@@ -166,6 +167,21 @@ def default_opts(**kw) -> COpts:
 
 def make_camera(cam) -> CCamera:
     return CCamera(cam.spin, cam.incl_deg, cam.r_cam, cam.fov_half, cam.nx, cam.ny, cam.t_frame)
+
+
+TRACE_KERNEL_SOURCES = ("trace.hip", "ks_geodesic.hpp", "plasma.hpp", "rt_math.hpp", "device_types.hpp",
+                        "mlp_device.hpp")
+
+
+def kernel_build_id():
+    """A digest of the sources the trace kernel is compiled from: measurements tied to one
+    kernel build (hardware counters) carry it, so that they are not reused after a change."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRACE_KERNEL_SOURCES:
+        with open(os.path.join(PKG, "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def work_per_unit():

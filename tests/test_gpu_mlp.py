@@ -65,7 +65,9 @@ def test_backward_matches_oracle(R, ctx, orc):
 
 
 def test_training_targets_match_oracle_closure(R, ctx, orc):
-    """ln j_hat of the exact closure on the device = ln(j / (n_e nu_c J0)) of the oracle."""
+    """ln j_hat of the exact closure on the device = ln(j / (n_e nu_c J0)) of the oracle, and
+    ln alpha_hat = ln j_hat - 2 ln x - ln Theta (Rayleigh-Jeans absorption in units of
+    n_e J0 / (2 m_e nu_c)), wherever the oracle's j does not underflow."""
     raw = S.mlp_samples(400, seed=S.S0 + 7).astype(np.float32)
     _, ex = R.mlp_closure(ctx, raw, net=False)
     B, ne = 10.0, 1.0
@@ -74,12 +76,11 @@ def test_training_targets_match_oracle_closure(R, ctx, orc):
     for i in range(raw.shape[0]):
         lx, lt, cb = (float(v) for v in raw[i])
         j, a = orc.closure(math.exp(lx) * nuc, ne, math.exp(lt), B, cb)
-        if j <= 0 or math.log(j / (ne * nuc * J0)) < -39.0:
-            assert ex[i, 0] == pytest.approx(-40.0, abs=1e-3) or (j > 0 and ex[i, 0] < -38.0)
+        if not j > 1e-290:
+            assert ex[i, 0] < -600.0
             continue
         lnj = math.log(j / (ne * nuc * J0))
         assert ex[i, 0] == pytest.approx(lnj, abs=2e-4 * max(1.0, abs(lnj)))
-        # Rayleigh-Jeans absorption in units of n_e J0 / (2 m_e nu_c): alpha_hat = j_hat / (x^2 Theta)
         assert ex[i, 1] == pytest.approx(lnj - 2 * lx - lt, abs=2e-4 * max(1.0, abs(lnj - 2 * lx - lt)))
         n_cmp += 1
     assert n_cmp > 200
@@ -120,3 +121,38 @@ def test_mlp_closure_in_trace_kernel(R, ctx):
         assert sm.ray_steps == sx.ray_steps and sm.samples == sx.samples
         assert np.isfinite(im).all() and fm[0] > 0
     ctx.release_grid(gh)
+
+
+def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
+    """The learned closure trained with the default configuration (1e7 samples) inside the
+    production render (9 images of 512^2, FP64 geodesics, FP32 transfer): total flux within
+    1e-3 of the exact closure for every image (the exact-closure render matches the oracle per
+    pixel, see the parity tests), and more accurate than the paper's K2 ~ 2 Theta^2
+    approximation of the same closure.  Throughput of the three closures is printed."""
+    R.mlp_init(ctx)
+    rep = R.mlp_train(ctx)
+    print(f"[mlp default training] {rep.as_dict()}", flush=True)
+    sets = S.production_set()
+    cams = [c for c, _ in sets]
+    handles, grids = {}, []
+    for c, g in sets:
+        if id(g) not in handles:
+            handles[id(g)] = ctx.upload_grid(g)
+        grids.append(handles[id(g)])
+    res = {}
+    for name, cl in (("exact", R.CLOSURE_EXACT), ("k2_paper", R.CLOSURE_K2_PAPER), ("mlp_split", R.CLOSURE_MLP),
+                     ("mlp_bf16", R.CLOSURE_MLP_BF16)):
+        opts = R.default_opts(transfer_prec=R.F32, closure=cl)
+        _, flux, st = ctx.trace_batch(cams, grids, [S.NU_230], opts)
+        res[name] = (np.asarray(flux).ravel(), st)
+    fx = res["exact"][0]
+    for name, (f, st) in res.items():
+        rel = f / fx - 1
+        print(f"[mlp gain] {name:9s} kernel_ms {st.kernel_ms:8.2f} ray-steps/s {st.ray_steps / st.kernel_ms * 1e3:.3e} "
+              f"max|dF/F| {np.abs(rel).max():.3e} fallback {st.n_mlp_fallback}/{st.samples}", flush=True)
+    e_mlp = np.abs(res["mlp_split"][0] / fx - 1)
+    e_k2 = np.abs(res["k2_paper"][0] / fx - 1)
+    assert e_mlp.max() <= 1e-3
+    assert e_mlp.max() < e_k2.min()
+    for h in handles.values():
+        ctx.release_grid(h)
