@@ -57,7 +57,9 @@ enum { RAPTOR_CLOSURE_EXACT = 0, RAPTOR_CLOSURE_K2_PAPER = 1, RAPTOR_CLOSURE_CON
        RAPTOR_CLOSURE_MLP = 3, RAPTOR_CLOSURE_MLP_BF16 = 4 };
 /* Ray termination codes written by raptor_trace_spectrum_ex. */
 enum { RAPTOR_RAY_HORIZON = 1, RAPTOR_RAY_ESCAPED = 2, RAPTOR_RAY_MAXSTEP = 3,
-       RAPTOR_RAY_NUMERIC = 4 };
+       RAPTOR_RAY_NUMERIC = 4, RAPTOR_RAY_OPAQUE = 5,
+       RAPTOR_RAY_DISK = 6,         /* thin-disk test: first equatorial crossing on the disk */
+       RAPTOR_RAY_PLANE = 7 };      /* thin-disk test: first equatorial crossing off the disk */
 
 enum { RAPTOR_MAX_NU = 32 };        /* frequencies per image */
 
@@ -116,19 +118,33 @@ typedef struct {
  * frequencies are uploaded before each replay.  Results are identical to the direct launch;
  * kernel_ms then spans the whole graph. */
 enum { RAPTOR_LAUNCH_DIRECT = 0, RAPTOR_LAUNCH_GRAPH = 1 };
+/* Geodesic integrators (Sec. 2.2): classical fourth-order Runge-Kutta (four connection
+ * evaluations per step), the second-order midpoint rule (two), and velocity Verlet (one; two
+ * with the corrector pass that re-evaluates the derivative with the updated wave vector).
+ * Verlet carries dk/dlambda from step to step and evaluates it afresh at the start of a ray
+ * and after a pole reflection.  The learned closure runs with RK4 only. */
+enum { RAPTOR_RK4 = 0, RAPTOR_RK2 = 1, RAPTOR_VERLET = 2, RAPTOR_VERLET_CORRECTED = 3 };
 typedef struct {
     double eps, r_stop_factor;
     int32_t max_steps, transfer_prec, closure, slow_light, mem, launch;
     double mass_msun, dist_pc, const_j, const_alpha, metric_mass;
+    int32_t integrator;          /* RAPTOR_RK4 (default), RAPTOR_RK2, RAPTOR_VERLET(_CORRECTED) */
+    int32_t reserved;            /* 0 */
+    double tau_cutoff;           /* > 0: a ray stops (RAPTOR_RAY_OPAQUE) after the first sample at
+                                    which its optical depth from the camera is >= tau_cutoff at
+                                    every frequency (Sec. 3.1: emission from further along reaches
+                                    the camera attenuated by at least exp(-tau_cutoff)); 0: off */
 } raptor_opts;
 
-/* Counters of the last trace call.  ray_steps counts accepted RK4 steps, samples the steps
- * at which the plasma was sampled, n_mlp_fallback the sample-frequencies that the learned
- * closure handed to the exact closure (inputs outside its box). */
+/* Counters of the last trace call.  ray_steps counts accepted steps, samples the plasma
+ * samples evaluated, n_mlp_fallback the sample-frequencies that the learned closure handed to
+ * the exact closure (inputs outside its box), n_opaque the rays stopped by the optical-depth
+ * cut-off. */
 typedef struct {
     uint64_t rays, ray_steps, samples, n_horizon, n_escaped, n_maxstep, n_pole, n_numeric,
              n_mlp_fallback, n_zamo_fallback;
     double kernel_ms;
+    uint64_t n_opaque;
 } raptor_stats;
 
 /* Fill *opts with the defaults: eps 0.05, r_stop_factor 1.01, max_steps 10000, FP64
@@ -168,9 +184,10 @@ raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int
                                  raptor_stats* stats);
 
 /* Launch plan of the persistent trace kernel: the autotuner's search space.  A plan is kept
- * per context for each (n_nu, transfer_prec) pair. */
+ * per context for each (n_nu class, transfer_prec, closure class) -- the closure class being
+ * the learned closures (RAPTOR_CLOSURE_MLP*) or the others. */
 typedef struct {
-    int32_t threads;             /* work-group size: 64, 128 or 256 */
+    int32_t threads;             /* work-group size: 64, 128, 256 or 512 */
     int32_t blocks_per_cu;       /* persistent work-groups per compute unit; 0 = as many as fit */
     int32_t refill_threshold;    /* a wave refills its idle lanes once this many are idle (1..64) */
     int32_t tile_width;          /* pixels per tile row: 8, 16, 32 or 64 (a tile is 64 rays) */
@@ -179,14 +196,20 @@ typedef struct {
     int32_t reserved[3];
 } raptor_plan;
 
-/* Current plan for (n_nu, transfer_prec) (the default plan if none was set or tuned). */
-raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, raptor_plan* out);
-/* Install a plan for (n_nu, transfer_prec); RAPTOR_E_INVALID if a field is out of range. */
-raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan);
+/* Current plan for (n_nu, transfer_prec, closure) (the default plan if none was set or tuned:
+ * 256 threads, as many work-groups as fit, refill at 1 idle lane, 8-pixel tile rows, the
+ * 2-waves-per-SIMD variant; 512 threads for the learned closures). */
+raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
+                              raptor_plan* out);
+/* Install a plan for (n_nu, transfer_prec, closure); RAPTOR_E_INVALID if a field is out of range,
+ * RAPTOR_E_UNSUPPORTED if no work-group of the plan fits the LDS. */
+raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
+                              const raptor_plan* plan);
 /* Autotuner: runs the given batch (arguments as raptor_trace_batch, outputs discarded) under
  * candidate plans by coordinate descent over the plan fields, timing each candidate with HIP
  * events as the fastest of `reps` runs, and installs the fastest plan for (n_nu,
- * opts->transfer_prec).  best and best_ms (the fastest kernel time) may be NULL. */
+ * opts->transfer_prec, opts->closure).  best and best_ms (the fastest kernel time) may be
+ * NULL. */
 raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
                                     const raptor_grid* const* grids, const raptor_opts* opts,
                                     const double* nu_hz, int32_t n_nu, int32_t reps, raptor_plan* best,
@@ -262,8 +285,30 @@ raptor_status raptor_mlp_closure(raptor_ctx* ctx, int32_t form, const float* raw
 /* Resources of the trace-kernel instantiation a plan selects: registers per lane, scratch
  * (spill) bytes per lane and resident work-groups per compute unit at the plan's work-group
  * size.  Any output pointer may be NULL. */
-raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan,
-                                 int32_t* vgprs, int32_t* scratch_bytes, int32_t* blocks_per_cu);
+raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
+                                 const raptor_plan* plan, int32_t* vgprs, int32_t* scratch_bytes,
+                                 int32_t* blocks_per_cu);
+
+/* ------------------------------------------------------------------------------------------
+ * Thin-disk line test (Sec. 4.2.1): a geometrically thin, optically thick Keplerian disk in the
+ * equatorial plane from the innermost stable circular orbit to r_disk_out, emitting a line
+ * with emission proportional to r^-2 and no absorption.  Each pixel's ray (integrator, eps,
+ * max_steps, r_stop_factor, metric_mass and mem taken from opts; closure must be EXACT, the
+ * plasma options are ignored) runs to its first crossing of the equatorial plane; the crossing
+ * is located by Newton iterations on theta(lambda), each an integrated partial step.  On the
+ * disk: redshift[p] = g = E_obs/E_em against the gas on prograde Keplerian circles
+ * (Omega = 1/(r^3/2 + a); a < 0 is a retrograde disk), intensity[p] = g^3 r^-2, status
+ * RAPTOR_RAY_DISK; a first crossing off the disk gives RAPTOR_RAY_PLANE and zeros (higher-order
+ * images are not counted).  profile[b] = sum over pixels with g in
+ * [g_lo + b w, g_lo + (b + 1) w), w = (g_hi - g_lo)/n_bins, of intensity * dalpha dbeta (M^2).
+ * Every output pointer may be NULL; outputs are host or device memory per opts->mem.
+ * stats: rays, ray_steps, samples = rays on the disk, kernel_ms.
+ * ------------------------------------------------------------------------------------------ */
+/* r_isco for signed spin (Bardeen, Press & Teukolsky 1972; a < 0: retrograde orbits). */
+raptor_status raptor_isco(double spin, double* r_isco);
+raptor_status raptor_trace_disk(raptor_ctx* ctx, const raptor_camera* cam, const raptor_opts* opts, double r_disk_out,
+                                int32_t n_bins, double g_lo, double g_hi, double* intensity, double* redshift,
+                                double* profile, int32_t* ray_status, int32_t* ray_steps, raptor_stats* stats);
 
 /* Algorithmic work per unit, counted once on the host by running the kernel's scalar
  * expressions through an operation-counting number type: FP64 add / sub / mul (a fused
@@ -275,6 +320,9 @@ raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer
  * which are not included in *_flops.  Any pointer may be NULL. */
 raptor_status raptor_work_per_unit(double* step_flops, double* step_special, double* sample_flops,
                                    double* sample_special, double* freq_flops, double* freq_special);
+/* The same count for one accepted step of the given integrator (RAPTOR_RK4 gives step_* above;
+ * a Verlet step excludes the occasional fresh derivative at a ray start or pole reflection). */
+raptor_status raptor_work_per_step(int32_t integrator, double* flops, double* special);
 
 #ifdef __cplusplus
 }

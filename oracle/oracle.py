@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libraptor_oracle.so")
 
 EXACT, K2_PAPER, CONST = 0, 1, 2
-RUNNING, HORIZON, ESCAPED, MAXSTEP, NUMERIC = 0, 1, 2, 3, 4
+RK4, RK2, VERLET, VERLET_CORR = 0, 1, 2, 3
+RUNNING, HORIZON, ESCAPED, MAXSTEP, NUMERIC, OPAQUE, DISK, PLANE = 0, 1, 2, 3, 4, 5, 6, 7
 
 DP = C.POINTER(C.c_double)
 
@@ -31,9 +32,9 @@ class Grid(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("r_stop_factor", C.c_double), ("max_steps", C.c_int32),
-                ("closure", C.c_int32), ("slow_light", C.c_int32), ("pad_", C.c_int32),
+                ("closure", C.c_int32), ("slow_light", C.c_int32), ("integrator", C.c_int32),
                 ("mass_msun", C.c_double), ("dist_pc", C.c_double), ("const_j", C.c_double),
-                ("const_alpha", C.c_double), ("metric_mass", C.c_double)]
+                ("const_alpha", C.c_double), ("metric_mass", C.c_double), ("tau_cutoff", C.c_double)]
 
 
 class RayInfo(C.Structure):
@@ -66,7 +67,16 @@ def lib():
         L.orc_step_size.restype = C.c_double
         L.orc_rk4_step.argtypes = [C.c_double, C.c_double, DP, C.c_double, DP]
         L.orc_integrate.argtypes = [C.c_double, C.c_double, DP, C.c_double, C.c_int, C.c_double,
-                                    C.c_double, DP, DP, C.c_int, C.POINTER(RayInfo)]
+                                    C.c_double, C.c_int, DP, DP, C.c_int, C.POINTER(RayInfo)]
+        L.orc_rk2_step.argtypes = [C.c_double, C.c_double, DP, C.c_double, DP]
+        L.orc_isco.argtypes = [C.c_double]
+        L.orc_isco.restype = C.c_double
+        L.orc_trace_disk_ray.argtypes = [C.POINTER(Camera), C.POINTER(Opts), C.c_double, C.c_double, C.c_double,
+                                         DP, DP, DP, C.POINTER(RayInfo)]
+        L.orc_trace_disk_image.argtypes = [C.POINTER(Camera), C.POINTER(Opts), C.c_double, DP, DP,
+                                           C.POINTER(RayInfo), C.c_int]
+        L.orc_disk_profile.argtypes = [C.POINTER(Camera), DP, DP, C.c_int, C.c_double, C.c_double, DP]
+        L.orc_verlet_step.argtypes = [C.c_double, C.c_double, DP, DP, C.c_double, C.c_int, DP]
         L.orc_integrate.restype = C.c_int
         L.orc_pixel_alpha_beta.argtypes = [C.POINTER(Camera), C.c_int, C.c_int, DP, DP]
         L.orc_camera_ray.argtypes = [C.POINTER(Camera), C.c_double, C.c_double, C.c_double, C.c_double, DP, DP]
@@ -130,9 +140,10 @@ class GridHandle:
 
 
 def make_opts(eps=0.05, r_stop_factor=1.01, max_steps=10000, closure=EXACT, slow_light=0,
-              mass_msun=4.5e6, dist_pc=8500.0, const_j=0.0, const_alpha=0.0, metric_mass=1.0) -> Opts:
-    return Opts(eps, r_stop_factor, max_steps, closure, slow_light, 0, mass_msun, dist_pc,
-                const_j, const_alpha, metric_mass)
+              mass_msun=4.5e6, dist_pc=8500.0, const_j=0.0, const_alpha=0.0, metric_mass=1.0,
+              integrator=0, tau_cutoff=0.0) -> Opts:
+    return Opts(eps, r_stop_factor, max_steps, closure, slow_light, integrator, mass_msun, dist_pc,
+                const_j, const_alpha, metric_mass, tau_cutoff)
 
 
 # ------------------------------------------------------------------------------------------
@@ -192,13 +203,29 @@ def rk4_step(a, M, y, dl):
     return out
 
 
-def integrate(a, M, y0, eps=0.05, max_steps=10000, r_stop=0.0, r_escape=1e4, cap=20000):
+def rk2_step(a, M, y, dl):
+    y = _f64(y, 8)
+    out = np.zeros(8)
+    lib().orc_rk2_step(a, M, _dp(y), dl, _dp(out))
+    return out
+
+
+def verlet_step(a, M, y, acc, dl, corrector=False):
+    """Returns (y_new, last evaluated derivative)."""
+    y = _f64(y, 8)
+    acc = _f64(acc, 4).copy()
+    out = np.zeros(8)
+    lib().orc_verlet_step(a, M, _dp(y), _dp(acc), dl, int(corrector), _dp(out))
+    return out, acc
+
+
+def integrate(a, M, y0, eps=0.05, max_steps=10000, r_stop=0.0, r_escape=1e4, cap=20000, integrator=RK4):
     y0 = _f64(y0, 8)
     traj = np.zeros((cap, 8))
     dls = np.zeros(cap)
     info = RayInfo()
-    n = lib().orc_integrate(a, M, _dp(y0), eps, max_steps, r_stop, r_escape, _dp(traj), _dp(dls), cap,
-                            C.byref(info))
+    n = lib().orc_integrate(a, M, _dp(y0), eps, max_steps, r_stop, r_escape, integrator, _dp(traj), _dp(dls),
+                            cap, C.byref(info))
     n = min(n, cap)
     return traj[:n], dls[:n], info
 
@@ -329,3 +356,42 @@ def mlp_backward(params, x, dy):
     dp = np.zeros(params.size)
     lib().orc_mlp_backward(_dp(params), _dp(x), _dp(dy), n, _dp(dp))
     return dp
+
+
+# ------------------------------------------------------------------------------------------
+# Thin disk (Sec. 4.2.1)
+# ------------------------------------------------------------------------------------------
+
+def isco(a):
+    return lib().orc_isco(a)
+
+
+def trace_disk_ray(cam, opts, r_disk_out, alpha, beta):
+    """(g, r_cross, I, info) of one ray of the thin-disk test."""
+    g, r, I = C.c_double(), C.c_double(), C.c_double()
+    info = RayInfo()
+    c = make_camera(cam)
+    lib().orc_trace_disk_ray(C.byref(c), C.byref(opts), r_disk_out, alpha, beta, C.byref(g), C.byref(r), C.byref(I),
+                             C.byref(info))
+    return g.value, r.value, I.value, info
+
+
+def trace_disk_image(cam, opts, r_disk_out=15.0, n_threads=0):
+    """(g [ny][nx], I [ny][nx], info [n][4] = status, steps, samples, poles)."""
+    n = cam.nx * cam.ny
+    g = np.zeros(n)
+    I = np.zeros(n)
+    info = (RayInfo * n)()
+    c = make_camera(cam)
+    lib().orc_trace_disk_image(C.byref(c), C.byref(opts), r_disk_out, _dp(g), _dp(I), info, n_threads)
+    arr = np.ctypeslib.as_array(info)
+    st = np.array([(r[0], r[1], r[2], r[3]) for r in arr], dtype=np.int64).reshape(-1, 4)
+    return g.reshape(cam.ny, cam.nx), I.reshape(cam.ny, cam.nx), st
+
+
+def disk_profile(cam, g, I, n_bins, g_lo, g_hi):
+    prof = np.zeros(n_bins)
+    c = make_camera(cam)
+    lib().orc_disk_profile(C.byref(c), _dp(np.ascontiguousarray(g, dtype=np.float64).ravel()),
+                           _dp(np.ascontiguousarray(I, dtype=np.float64).ravel()), n_bins, g_lo, g_hi, _dp(prof))
+    return prof

@@ -201,6 +201,61 @@ void orc_rk4_step(double a, double M, const double y[8], double dl, double yout[
     }
 }
 
+/* Second-order Runge-Kutta (midpoint) step.  The paper names RK2 only for its timing runs;
+ * the midpoint rule is the reading taken here: C1 = dl f(y), y_new = y + dl f(y + C1/2). */
+void orc_rk2_step(double a, double M, const double y[8], double dl, double yout[8])
+{
+    double c1[8], c2[8], t[8];
+    orc_geodesic_rhs(a, M, y, c1);
+    for (int i = 0; i < 8; ++i) t[i] = y[i] + 0.5 * dl * c1[i];
+    orc_geodesic_rhs(a, M, t, c2);
+    for (int i = 0; i < 8; ++i) yout[i] = y[i] + dl * c2[i];
+}
+
+/* Velocity Verlet step, Sec. 2.2.2: with A_n = (dk/dlambda)_n,
+ *   x_{n+1} = x_n + k_n dl + A_n dl^2 / 2,   k_p = k_n + A_n dl,
+ *   A_{n+1} = -Gamma(x_{n+1}) k_p k_p,       k_{n+1} = k_n + (A_n + A_{n+1}) dl / 2,
+ * and with the corrector the derivative is evaluated once more with k_p = k_{n+1} and the last
+ * line repeated.  acc holds A_n on entry and the last evaluated derivative on return. */
+void orc_verlet_step(double a, double M, const double y[8], double acc[4], double dl, int corrector,
+                     double yout[8])
+{
+    double t[8], f[8];
+    for (int i = 0; i < 4; ++i) {
+        t[i] = y[i] + y[4 + i] * dl + 0.5 * acc[i] * dl * dl;
+        t[4 + i] = y[4 + i] + acc[i] * dl;
+    }
+    orc_geodesic_rhs(a, M, t, f);
+    for (int i = 0; i < 4; ++i) t[4 + i] = y[4 + i] + 0.5 * (acc[i] + f[4 + i]) * dl;
+    if (corrector) {
+        orc_geodesic_rhs(a, M, t, f);
+        for (int i = 0; i < 4; ++i) t[4 + i] = y[4 + i] + 0.5 * (acc[i] + f[4 + i]) * dl;
+    }
+    for (int i = 0; i < 4; ++i) acc[i] = f[4 + i];
+    memcpy(yout, t, 8 * sizeof(double));
+}
+
+/* One step of the chosen integrator.  Verlet carries the derivative from step to step in
+ * acc; *have_acc = 0 asks for it to be evaluated at y first (start of a ray, or after a pole
+ * reflection changed the chart). */
+static void geo_step(double a, double M, int integrator, const double y[8], double acc[4], int* have_acc,
+                     double dl, double yout[8])
+{
+    if (integrator == ORC_RK2) {
+        orc_rk2_step(a, M, y, dl, yout);
+    } else if (integrator == ORC_VERLET || integrator == ORC_VERLET_CORR) {
+        if (!*have_acc) {
+            double f[8];
+            orc_geodesic_rhs(a, M, y, f);
+            for (int i = 0; i < 4; ++i) acc[i] = f[4 + i];
+        }
+        orc_verlet_step(a, M, y, acc, dl, integrator == ORC_VERLET_CORR, yout);
+        *have_acc = 1;
+    } else {
+        orc_rk4_step(a, M, y, dl, yout);
+    }
+}
+
 static int state_finite(const double y[8])
 {
     for (int i = 0; i < 8; ++i)
@@ -236,19 +291,20 @@ static int termination(const double y[8], int steps, int max_steps, double r_sto
 }
 
 int orc_integrate(double a, double M, const double y0[8], double eps, int max_steps,
-                  double r_stop, double r_escape, double* traj, double* dls, int cap,
+                  double r_stop, double r_escape, int integrator, double* traj, double* dls, int cap,
                   orc_ray_info* info)
 {
-    double y[8], yn[8];
+    double y[8], yn[8], acc[4];
+    int have_acc = 0;
     memcpy(y, y0, sizeof y);
     int steps = 0, poles = 0, status = ORC_RUNNING;
     while (status == ORC_RUNNING) {
         double dl = -orc_step_size(eps, y, y + 4);
-        orc_rk4_step(a, M, y, dl, yn);
+        geo_step(a, M, integrator, y, acc, &have_acc, dl, yn);
         memcpy(y, yn, sizeof y);
         ++steps;
         if (!state_finite(y)) { status = ORC_NUMERIC; break; }
-        poles += reflect_pole(y);
+        if (reflect_pole(y)) { ++poles; have_acc = 0; }
         if (traj && steps <= cap) {
             memcpy(traj + 8 * (steps - 1), y, sizeof y);
             if (dls) dls[steps - 1] = dl;
@@ -257,6 +313,103 @@ int orc_integrate(double a, double M, const double y0[8], double eps, int max_st
     }
     if (info) { info->status = status; info->steps = steps; info->samples = 0; info->poles = poles; }
     return steps;
+}
+
+/* ===================================================================================== */
+/* Thin accretion disk (Sec. 4.2.1)                                                     */
+/* ===================================================================================== */
+
+/* Innermost stable circular orbit (Bardeen, Press & Teukolsky 1972):
+ * r = 3 + Z2 - sign(a) sqrt((3 - Z1)(3 + Z1 + 2 Z2)),
+ * Z1 = 1 + (1 - a^2)^(1/3) ((1 + a)^(1/3) + (1 - a)^(1/3)), Z2 = sqrt(3 a^2 + Z1^2). */
+double orc_isco(double a)
+{
+    double z1 = 1.0 + cbrt(1.0 - a * a) * (cbrt(1.0 + a) + cbrt(1.0 - a));
+    double z2 = sqrt(3.0 * a * a + z1 * z1);
+    double s = a >= 0.0 ? 1.0 : -1.0;
+    return 3.0 + z2 - s * sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
+}
+
+/* The crossing point (reading: the paper does not say how crossings are located): when a step
+ * from y to y' brackets theta = pi/2, the affine parameter of the crossing is estimated by
+ * linear interpolation of theta, then refined by two Newton iterations on theta(lambda), each
+ * integrating one step of that length from y with the same integrator (dtheta/dlambda = k^theta).
+ * The crossing state is thus an integrated state, on which k_t and k_phi keep their conserved
+ * values.  The disk gas moves on prograde Keplerian circles, Omega = 1/(r^(3/2) + a). */
+void orc_trace_disk_ray(const orc_camera* cam, const orc_opts* o, double r_disk_out, double alpha, double beta,
+                        double* g, double* r_cross, double* Iv, orc_ray_info* info)
+{
+    double M = o->metric_mass, a = cam->spin;
+    double rh = M + sqrt(M * M - a * a);
+    double r_stop = o->r_stop_factor * rh;
+    double r_in = orc_isco(a);
+    double y[8], yn[8], acc[4], acc0[4];
+    int have_acc = 0;
+    orc_camera_ray(cam, M, alpha, beta, 0.0, y, NULL);
+    int steps = 0, poles = 0, status = ORC_RUNNING;
+    *g = 0.0; *r_cross = 0.0; *Iv = 0.0;
+    while (status == ORC_RUNNING) {
+        double dl = -orc_step_size(o->eps, y, y + 4);
+        int had_acc = have_acc;
+        memcpy(acc0, acc, sizeof acc);
+        geo_step(a, M, o->integrator, y, acc, &have_acc, dl, yn);
+        ++steps;
+        if (!state_finite(yn)) { status = ORC_NUMERIC; break; }
+        double h0 = y[2] - 0.5 * M_PI, h1 = yn[2] - 0.5 * M_PI;
+        if (h0 * h1 < 0.0) {
+            double lam = dl * h0 / (h0 - h1), yc[8], ac[4];
+            for (int it = 0; it < 3; ++it) {
+                int hc = had_acc;
+                memcpy(ac, acc0, sizeof ac);
+                geo_step(a, M, o->integrator, y, ac, &hc, lam, yc);
+                if (it < 2) lam += (0.5 * M_PI - yc[2]) / yc[6];
+            }
+            *r_cross = yc[1];
+            if (yc[1] >= r_in && yc[1] <= r_disk_out) {
+                double u[4], b[4], nr, cb;
+                double omega = 1.0 / (pow(yc[1], 1.5) + a);
+                orc_fluid_frame(a, M, yc, yc + 4, omega, u, b, &nr, &cb);
+                *g = 1.0 / nr;
+                *Iv = (*g) * (*g) * (*g) / (yc[1] * yc[1]);
+                status = ORC_DISK;
+            } else {
+                status = ORC_PLANE;
+            }
+            break;
+        }
+        memcpy(y, yn, sizeof y);
+        if (reflect_pole(y)) { ++poles; have_acc = 0; }
+        status = termination(y, steps, o->max_steps, r_stop, cam->r_cam);
+    }
+    if (info) { info->status = status; info->steps = steps; info->samples = 0; info->poles = poles; }
+}
+
+void orc_trace_disk_image(const orc_camera* cam, const orc_opts* o, double r_disk_out, double* g, double* Iv,
+                          orc_ray_info* info, int n_threads)
+{
+    long n = (long)cam->nx * cam->ny;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+#endif
+    for (long p = 0; p < n; ++p) {
+        double al, be, rc;
+        orc_pixel_alpha_beta(cam, (int)(p % cam->nx), (int)(p / cam->nx), &al, &be);
+        orc_trace_disk_ray(cam, o, r_disk_out, al, be, &g[p], &rc, &Iv[p], info ? &info[p] : NULL);
+    }
+}
+
+void orc_disk_profile(const orc_camera* cam, const double* g, const double* Iv, int n_bins, double g_lo,
+                      double g_hi, double* profile)
+{
+    double dA = (2.0 * cam->fov_half / cam->nx) * (2.0 * cam->fov_half / cam->ny);
+    for (int b = 0; b < n_bins; ++b) profile[b] = 0.0;
+    for (long p = 0; p < (long)cam->nx * cam->ny; ++p) {
+        if (!(Iv[p] > 0.0)) continue;
+        double q = (g[p] - g_lo) / (g_hi - g_lo) * n_bins;
+        if (q < 0.0 || q >= n_bins) continue;
+        profile[(int)q] += Iv[p] * dA;
+    }
 }
 
 /* ===================================================================================== */
@@ -549,18 +702,19 @@ void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* 
     double rh = M + sqrt(M * M - a * a);
     double r_stop = o->r_stop_factor * rh;
     double Lu = orc_length_unit(o->mass_msun);
-    double y[8], yn[8];
+    double y[8], yn[8], acc[4];
+    int have_acc = 0;
     orc_camera_ray(cam, M, alpha, beta, cam->t_frame + cam->r_cam, y, NULL);
     double tau[64];
     for (int f = 0; f < n_nu; ++f) { Iout[f] = 0.0; tau[f] = 0.0; }
     int steps = 0, samples = 0, poles = 0, status = ORC_RUNNING;
     while (status == ORC_RUNNING) {
         double dl = -orc_step_size(o->eps, y, y + 4);
-        orc_rk4_step(a, M, y, dl, yn);
+        geo_step(a, M, o->integrator, y, acc, &have_acc, dl, yn);
         memcpy(y, yn, sizeof y);
         ++steps;
         if (!state_finite(y)) { status = ORC_NUMERIC; break; }
-        poles += reflect_pole(y);
+        if (reflect_pole(y)) { ++poles; have_acc = 0; }
         status = termination(y, steps, o->max_steps, r_stop, cam->r_cam);
         orc_step_rec* rr = (rec && steps <= rec_cap) ? &rec[steps - 1] : NULL;
         if (rr) {
@@ -584,6 +738,14 @@ void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* 
             Iout[f] += add;
             tau[f] += dtau;
             if (rr && f == 0) { rr->sampled = 1; rr->nu_r = nr; rr->j = jv; rr->alpha = av; rr->ds = ds; }
+        }
+        /* optical-depth cut-off (Sec. 3.1, backward scheme): once the material between the
+         * point and the camera is opaque at every frequency, emission from further along the
+         * ray reaches the camera attenuated by at least exp(-tau_cutoff) and the ray stops */
+        if (o->tau_cutoff > 0.0) {
+            double tmin = tau[0];
+            for (int f = 1; f < n_nu; ++f) tmin = fmin(tmin, tau[f]);
+            if (tmin >= o->tau_cutoff) { status = ORC_OPAQUE; break; }
         }
     }
     if (status == ORC_NUMERIC)

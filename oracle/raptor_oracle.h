@@ -29,12 +29,18 @@ typedef struct {
 } orc_grid;
 
 enum { ORC_CLOSURE_EXACT = 0, ORC_CLOSURE_K2_PAPER = 1, ORC_CLOSURE_CONST = 2 };
-enum { ORC_RUNNING = 0, ORC_HORIZON = 1, ORC_ESCAPED = 2, ORC_MAXSTEP = 3, ORC_NUMERIC = 4 };
+enum { ORC_RUNNING = 0, ORC_HORIZON = 1, ORC_ESCAPED = 2, ORC_MAXSTEP = 3, ORC_NUMERIC = 4, ORC_OPAQUE = 5,
+       ORC_DISK = 6, ORC_PLANE = 7 };
+
+/* integrators of the geodesic (Sec. 2.2): classical RK4, the second-order midpoint rule, and
+ * velocity Verlet without and with the corrector pass */
+enum { ORC_RK4 = 0, ORC_RK2 = 1, ORC_VERLET = 2, ORC_VERLET_CORR = 3 };
 
 typedef struct {
     double eps, r_stop_factor;
-    int32_t max_steps, closure, slow_light, pad_;
+    int32_t max_steps, closure, slow_light, integrator;
     double mass_msun, dist_pc, const_j, const_alpha, metric_mass;
+    double tau_cutoff;               /* > 0: stop a ray once tau >= tau_cutoff at every frequency */
 } orc_opts;
 
 typedef struct {
@@ -57,9 +63,14 @@ void orc_christoffel(double a, double M, const double x[4], double gam[64]);
 void orc_geodesic_rhs(double a, double M, const double y[8], double f[8]);
 double orc_step_size(double eps, const double x[4], const double k[4]);
 void orc_rk4_step(double a, double M, const double y[8], double dl, double yout[8]);
-/* integrate from y0 with the paper's step rule; records up to cap states (after each step) */
+void orc_rk2_step(double a, double M, const double y[8], double dl, double yout[8]);
+/* velocity Verlet; acc: dk/dlambda at y on entry, the last evaluated derivative on return */
+void orc_verlet_step(double a, double M, const double y[8], double acc[4], double dl, int corrector,
+                     double yout[8]);
+/* integrate from y0 with the paper's step rule and the given integrator (ORC_RK4 ...); records
+ * up to cap states (after each step) */
 int  orc_integrate(double a, double M, const double y0[8], double eps, int max_steps,
-                   double r_stop, double r_escape, double* traj, double* dls, int cap,
+                   double r_stop, double r_escape, int integrator, double* traj, double* dls, int cap,
                    orc_ray_info* info);
 
 /* camera ----------------------------------------------------------------------------- */
@@ -79,6 +90,23 @@ double orc_bessel_k2(double x);
 void orc_closure(int mode, double nu, double ne, double thetae, double bfield, double cos_b,
                  double const_j, double const_alpha, double* j, double* alpha);
 double orc_planck(double nu, double thetae);
+
+/* thin disk (Sec. 4.2.1) ------------------------------------------------------------------ */
+/* radius of the innermost stable circular orbit for signed spin a (a < 0: retrograde disk) */
+double orc_isco(double a);
+/* One ray of the thin-disk test: integrate until the first crossing of the equatorial plane.
+ * If it lands on the disk (r_isco <= r <= r_disk_out) the status is ORC_DISK, *g the ratio
+ * E_obs/E_em against the Keplerian disk and *I = g^3 r^-2 (emission proportional to r^-2, no
+ * absorption); a first crossing off the disk gives ORC_PLANE and I = 0 (higher-order images
+ * are not counted), any other end the usual status and I = 0. */
+void orc_trace_disk_ray(const orc_camera* cam, const orc_opts* o, double r_disk_out, double alpha, double beta,
+                        double* g, double* r_cross, double* Iv, orc_ray_info* info);
+/* every pixel of cam (OpenMP over pixels); g, I: [ny][nx]; info may be NULL */
+void orc_trace_disk_image(const orc_camera* cam, const orc_opts* o, double r_disk_out, double* g, double* Iv,
+                          orc_ray_info* info, int n_threads);
+/* line profile: profile[b] = sum over pixels with g in bin b of I * dalpha dbeta (M^2) */
+void orc_disk_profile(const orc_camera* cam, const double* g, const double* Iv, int n_bins, double g_lo,
+                      double g_hi, double* profile);
 
 /* transfer and products ---------------------------------------------------------------- */
 void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,

@@ -36,7 +36,7 @@ struct K2Table {
 
 enum : int {
     ST_RAYS = 0, ST_STEPS, ST_SAMPLES, ST_HORIZON, ST_ESCAPED, ST_MAXSTEP, ST_POLE, ST_NUMERIC,
-    ST_MLP_FALLBACK, ST_ZAMO, ST_COUNT
+    ST_MLP_FALLBACK, ST_ZAMO, ST_OPAQUE, ST_COUNT
 };
 
 struct TraceParams {
@@ -50,9 +50,9 @@ struct TraceParams {
     unsigned long long* stats; // ST_COUNT counters
     K2Table k2;
     long long n_tiles;
-    int n_jobs, max_steps, closure, slow_light;
+    int n_jobs, max_steps, closure, slow_light, integrator, pad;
     int refill_threshold, tile_shift;   // tile width = 1 << tile_shift pixels, height 64 / width
-    double eps, M, length_unit, const_j, const_alpha;
+    double eps, M, length_unit, const_j, const_alpha, tau_cutoff;
     // learned closure (closure == CL_MLP): FP32 parameters and padded BF16 hi / lo weights
     const float* mlp_P;
     const unsigned short* mlp_W;
@@ -61,4 +61,18 @@ struct TraceParams {
 
 // CL_MLP evaluates the network in split BF16 form, CL_MLP_BF16 in plain BF16 form
 enum : int { CL_EXACT = 0, CL_K2_PAPER = 1, CL_CONST = 2, CL_MLP = 3, CL_MLP_BF16 = 4 };
-enum : int { RAY_RUNNING = 0, RAY_HORIZON = 1, RAY_ESCAPED = 2, RAY_MAXSTEP = 3, RAY_NUMERIC = 4 };
+enum : int { RAY_RUNNING = 0, RAY_HORIZON = 1, RAY_ESCAPED = 2, RAY_MAXSTEP = 3, RAY_NUMERIC = 4, RAY_OPAQUE = 5,
+             RAY_DISK = 6, RAY_PLANE = 7 };
+// geodesic integrators (INTEG_VERLET_CORR runs the Verlet kernel with the corrector pass)
+enum : int { INTEG_RK4 = 0, INTEG_RK2 = 1, INTEG_VERLET = 2, INTEG_VERLET_CORR = 3 };
+
+// Thin-disk test: one camera, Keplerian disk between r_in (the ISCO) and r_out.
+struct DiskParams {
+    double a, incl, sin_i, cos_i, r_cam, fov, dalpha, dbeta, r_stop, r_in, r_out, eps, M;
+    int nx, ny, max_steps, integrator;
+    double* intensity;            // [ny][nx] or null
+    double* redshift;             // [ny][nx] or null
+    int* status;                  // [ny][nx] or null
+    int* steps;                   // [ny][nx] or null
+    unsigned long long* stats;    // [0] ray-steps, [1] rays on the disk
+};

@@ -87,6 +87,12 @@ raptor_status check_opts(raptor_ctx* ctx, const raptor_opts* o)
     if (o->mem != RAPTOR_MEM_HOST && o->mem != RAPTOR_MEM_DEVICE) return fail(ctx, RAPTOR_E_INVALID, "unknown mem");
     if (o->launch != RAPTOR_LAUNCH_DIRECT && o->launch != RAPTOR_LAUNCH_GRAPH)
         return fail(ctx, RAPTOR_E_INVALID, "unknown launch mode");
+    if (o->integrator < RAPTOR_RK4 || o->integrator > RAPTOR_VERLET_CORRECTED)
+        return fail(ctx, RAPTOR_E_INVALID, "unknown integrator");
+    if (!(std::isfinite(o->tau_cutoff) && o->tau_cutoff >= 0.0))
+        return fail(ctx, RAPTOR_E_INVALID, "tau_cutoff must be finite and >= 0");
+    if (o->integrator != RAPTOR_RK4 && o->closure >= RAPTOR_CLOSURE_MLP)
+        return fail(ctx, RAPTOR_E_UNSUPPORTED, "the learned closure runs with the RK4 integrator only");
     if (!finite_pos(o->mass_msun) || !finite_pos(o->dist_pc))
         return fail(ctx, RAPTOR_E_INVALID, "mass_msun and dist_pc must be positive");
     if (o->metric_mass != 0.0 && o->metric_mass != 1.0) return fail(ctx, RAPTOR_E_INVALID, "metric_mass must be 0 or 1");
@@ -134,7 +140,7 @@ struct JobIn {
 bool plan_valid(const raptor_plan& p)
 {
     const bool tw = p.tile_width == 8 || p.tile_width == 16 || p.tile_width == 32 || p.tile_width == 64;
-    return (p.threads == 64 || p.threads == 128 || p.threads == 256) && p.blocks_per_cu >= 0 &&
+    return (p.threads == 64 || p.threads == 128 || p.threads == 256 || p.threads == 512) && p.blocks_per_cu >= 0 &&
            p.blocks_per_cu <= 64 && p.refill_threshold >= 1 && p.refill_threshold <= 64 && tw &&
            (p.min_waves_per_simd >= 1 && p.min_waves_per_simd <= 3);
 }
@@ -149,6 +155,13 @@ int plan_key(int n_nu, bool fp32, bool mlpc)
 // resident at once when 0.
 raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* pl, bool mlpc = false)
 {
+    // the work-group size the instantiation allows (512 lanes only for the learned closure's
+    // 2-waves-per-SIMD variant)
+    int regs = 0, spill = 0, max_threads = 0;
+    RAPTOR_CK(trace_kernel_attributes(max_nu, fp32, pl->p.min_waves_per_simd, mlpc, INTEG_RK4, &regs, &spill,
+                                      &max_threads),
+              "reading kernel attributes");
+    while (pl->p.threads > 64 && pl->p.threads > max_threads) pl->p.threads /= 2;
     // the per-wave sample queue lives in LDS: shrink the work-group until it fits
     while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc) > ctx->lds_per_block)
         pl->p.threads /= 2;
@@ -175,6 +188,7 @@ raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, 
         return RAPTOR_OK;
     }
     LaunchPlan pl;
+    if (mlpc) pl.p.threads = 512;   // eight waves share one LDS copy of the network
     raptor_status s = resolve_plan(ctx, max_nu, fp32, &pl, mlpc);
     if (s != RAPTOR_OK) return s;
     ctx->plans[key] = pl;
@@ -364,11 +378,13 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     p.max_steps = o->max_steps;
     p.closure = o->closure;
     p.slow_light = o->slow_light;
+    p.integrator = o->integrator;
     p.eps = o->eps;
     p.M = M;
     p.length_unit = Lu;
     p.const_j = o->const_j;
     p.const_alpha = o->const_alpha;
+    p.tau_cutoff = o->tau_cutoff;
     p.mlp_P = ctx->mlp.P.p;
     p.mlp_W = ctx->mlp.W.p;
     p.mlp_Wlo = ctx->mlp.Wlo.p;
@@ -411,6 +427,7 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
         st->n_numeric = hs[ST_NUMERIC];
         st->n_mlp_fallback = hs[ST_MLP_FALLBACK];
         st->n_zamo_fallback = hs[ST_ZAMO];
+        st->n_opaque = hs[ST_OPAQUE];
         float ms = 0.0f;
         RAPTOR_CK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "reading the kernel time");
         st->kernel_ms = ms;
@@ -531,6 +548,7 @@ raptor_status raptor_default_opts(raptor_opts* o)
     o->mass_msun = 4.5e6;
     o->dist_pc = 8500.0;
     o->metric_mass = 1.0;
+    o->integrator = RAPTOR_RK4;
     return RAPTOR_OK;
 }
 
@@ -688,33 +706,38 @@ raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int
     return run_jobs(ctx, in, n_nu, opts, images, flux_jy, nullptr, nullptr, stats);
 }
 
-raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, raptor_plan* out)
+raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
+                              raptor_plan* out)
 {
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
-    if (!out || n_nu < 1 || n_nu > RAPTOR_MAX_NU || (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64))
+    if (!out || n_nu < 1 || n_nu > RAPTOR_MAX_NU || (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64) ||
+        closure < RAPTOR_CLOSURE_EXACT || closure > RAPTOR_CLOSURE_MLP_BF16)
         return fail(ctx, RAPTOR_E_INVALID, "bad arguments to raptor_get_plan");
     LaunchPlan pl;
-    raptor_status s = plan_for(ctx, n_nu, transfer_prec == RAPTOR_F32, &pl);
+    raptor_status s = plan_for(ctx, n_nu, transfer_prec == RAPTOR_F32, &pl, closure >= RAPTOR_CLOSURE_MLP);
     if (s != RAPTOR_OK) return s;
     *out = pl.p;
     return RAPTOR_OK;
 }
 
-raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan)
+raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
+                              const raptor_plan* plan)
 {
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
-    if (!plan || n_nu < 1 || n_nu > RAPTOR_MAX_NU || (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64))
+    if (!plan || n_nu < 1 || n_nu > RAPTOR_MAX_NU || (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64) ||
+        closure < RAPTOR_CLOSURE_EXACT || closure > RAPTOR_CLOSURE_MLP_BF16)
         return fail(ctx, RAPTOR_E_INVALID, "bad arguments to raptor_set_plan");
     if (!plan_valid(*plan)) return fail(ctx, RAPTOR_E_INVALID, "plan field out of range");
     LaunchPlan pl;
     pl.p = *plan;
     const bool fp32 = transfer_prec == RAPTOR_F32;
+    const bool mlpc = closure >= RAPTOR_CLOSURE_MLP;
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
-    raptor_status s = resolve_plan(ctx, n_nu, fp32, &pl);
+    raptor_status s = resolve_plan(ctx, n_nu, fp32, &pl, mlpc);
     if (s != RAPTOR_OK) return s;
-    ctx->plans[plan_key(n_nu, fp32, false)] = pl;
+    ctx->plans[plan_key(n_nu, fp32, mlpc)] = pl;
     return RAPTOR_OK;
 }
 
@@ -754,7 +777,7 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     double bms;
     if ((s = time_plan(bp, &bms)) != RAPTOR_OK) return s;
     // coordinate descent over the plan fields
-    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256}, {0, 2, 4}, {1, 8, 16, 32}, {8, 16, 64}};
+    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256, 512}, {0, 2, 4}, {1, 8, 16, 32}, {8, 16, 64}};
     for (int field = 0; field < (int)values.size(); ++field) {
         for (int v : values[field]) {
             raptor_plan c = bp;
@@ -780,26 +803,170 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     return RAPTOR_OK;
 }
 
-raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, const raptor_plan* plan,
-                                 int32_t* vgprs, int32_t* scratch_bytes, int32_t* blocks_per_cu)
+raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
+                                 const raptor_plan* plan, int32_t* vgprs, int32_t* scratch_bytes,
+                                 int32_t* blocks_per_cu)
 {
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
     if (!plan || !plan_valid(*plan) || n_nu < 1 || n_nu > RAPTOR_MAX_NU ||
-        (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64))
+        (transfer_prec != RAPTOR_F32 && transfer_prec != RAPTOR_F64) || closure < RAPTOR_CLOSURE_EXACT ||
+        closure > RAPTOR_CLOSURE_MLP_BF16)
         return fail(ctx, RAPTOR_E_INVALID, "bad arguments to raptor_kernel_info");
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
     const bool fp32 = transfer_prec == RAPTOR_F32;
+    const bool mlpc = closure >= RAPTOR_CLOSURE_MLP;
     int regs = 0, spill = 0, maxt = 0, per_cu = 0;
-    RAPTOR_CK(trace_kernel_attributes(n_nu, fp32, plan->min_waves_per_simd, false, &regs, &spill, &maxt),
+    RAPTOR_CK(trace_kernel_attributes(n_nu, fp32, plan->min_waves_per_simd, mlpc, INTEG_RK4, &regs, &spill, &maxt),
               "reading kernel attributes");
     RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd), plan->threads,
-                  trace_kernel_lds(n_nu, fp32, plan->threads, false)),
+                  &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd, mlpc), plan->threads,
+                  trace_kernel_lds(n_nu, fp32, plan->threads, mlpc)),
               "querying occupancy");
     if (vgprs) *vgprs = regs;
     if (scratch_bytes) *scratch_bytes = spill;
     if (blocks_per_cu) *blocks_per_cu = per_cu;
+    return RAPTOR_OK;
+}
+
+static double isco_radius(double a)
+{
+    // Bardeen, Press & Teukolsky: prograde for a >= 0, retrograde for a < 0
+    const double z1 = 1.0 + std::cbrt(1.0 - a * a) * (std::cbrt(1.0 + a) + std::cbrt(1.0 - a));
+    const double z2 = std::sqrt(3.0 * a * a + z1 * z1);
+    return 3.0 + z2 - (a >= 0.0 ? 1.0 : -1.0) * std::sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
+}
+
+raptor_status raptor_isco(double spin, double* r_isco)
+{
+    if (!r_isco || !(std::fabs(spin) < 1.0)) return RAPTOR_E_INVALID;
+    *r_isco = isco_radius(spin);
+    return RAPTOR_OK;
+}
+
+raptor_status raptor_trace_disk(raptor_ctx* ctx, const raptor_camera* cam, const raptor_opts* opts, double r_disk_out,
+                                int32_t n_bins, double g_lo, double g_hi, double* intensity, double* redshift,
+                                double* profile, int32_t* ray_status, int32_t* ray_steps, raptor_stats* stats)
+{
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    raptor_status s;
+    if (!cam) return fail(ctx, RAPTOR_E_INVALID, "camera is NULL");
+    if ((s = check_opts(ctx, opts)) != RAPTOR_OK) return s;
+    if (opts->closure != RAPTOR_CLOSURE_EXACT)
+        return fail(ctx, RAPTOR_E_INVALID, "the thin-disk test has its own emission (closure must be EXACT)");
+    if (!(std::fabs(cam->spin) < 1.0) || !(cam->incl_deg > 0.0 && cam->incl_deg < 180.0) || cam->nx < 1 ||
+        cam->ny < 1 || !finite_pos(cam->fov_half) || !std::isfinite(cam->r_cam))
+        return fail(ctx, RAPTOR_E_INVALID, "bad camera");
+    const double M = opts->metric_mass;
+    const double rh = M + std::sqrt(std::max(M * M - cam->spin * cam->spin, 0.0));
+    const double r_in = isco_radius(cam->spin);
+    if (!(r_disk_out > r_in) || !(cam->r_cam > r_disk_out) || !(cam->r_cam > opts->r_stop_factor * rh))
+        return fail(ctx, RAPTOR_E_INVALID, "need r_isco < r_disk_out < r_cam and r_cam outside the horizon");
+    if (profile && (n_bins < 1 || n_bins > (1 << 20) || !(g_hi > g_lo) || !std::isfinite(g_lo) || !std::isfinite(g_hi)))
+        return fail(ctx, RAPTOR_E_INVALID, "bad profile binning");
+    const long long n = (long long)cam->nx * cam->ny;
+    if (n > (1ll << 31)) return fail(ctx, RAPTOR_E_RANGE, "too many pixels");
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    const bool dev = opts->mem == RAPTOR_MEM_DEVICE;
+    // device buffers: the caller's in device mode, the context's otherwise (the profile needs
+    // both images)
+    double *dI = intensity, *dG = redshift;
+    int *dS = ray_status, *dN = ray_steps;
+    if (!dev || !intensity || !redshift) {
+        RAPTOR_CK(ctx->out.reserve(2 * n), "allocating images");
+        if (!dev || !intensity) dI = ctx->out.p;
+        if (!dev || !redshift) dG = ctx->out.p + n;
+    }
+    if (!dev && (ray_status || ray_steps)) {
+        RAPTOR_CK(ctx->status.reserve(n), "allocating ray info");
+        RAPTOR_CK(ctx->steps.reserve(n), "allocating ray info");
+        dS = ray_status ? ctx->status.p : nullptr;
+        dN = ray_steps ? ctx->steps.p : nullptr;
+    }
+    double* dP = nullptr;
+    if (profile) {
+        if (dev) {
+            dP = profile;
+        } else {
+            RAPTOR_CK(ctx->flux_part.reserve((size_t)n_bins), "allocating the profile");
+            dP = ctx->flux_part.p;
+        }
+    }
+    DiskParams p;
+    std::memset(&p, 0, sizeof p);
+    p.a = cam->spin;
+    p.incl = cam->incl_deg * kPi / 180.0;
+    p.sin_i = std::sin(p.incl);
+    p.cos_i = std::cos(p.incl);
+    p.r_cam = cam->r_cam;
+    p.fov = cam->fov_half;
+    p.dalpha = 2.0 * cam->fov_half / cam->nx;
+    p.dbeta = 2.0 * cam->fov_half / cam->ny;
+    p.r_stop = opts->r_stop_factor * rh;
+    p.r_in = r_in;
+    p.r_out = r_disk_out;
+    p.eps = opts->eps;
+    p.M = M;
+    p.nx = cam->nx;
+    p.ny = cam->ny;
+    p.max_steps = opts->max_steps;
+    p.integrator = opts->integrator;
+    p.intensity = dI;
+    p.redshift = dG;
+    p.status = dS;
+    p.steps = dN;
+    p.stats = ctx->stats.p;
+    hipStream_t st = ctx->stream;
+    RAPTOR_CK(launch_reset(ctx->counter.p, ctx->stats.p, st), "launching reset");
+    const int blocks = (int)std::min<long long>((n + 255) / 256, (long long)ctx->cu_count * 8);
+    RAPTOR_CK(hipEventRecord(ctx->ev0, st), "recording an event");
+    RAPTOR_CK(launch_disk(p, blocks, st), "launching the disk kernel");
+    RAPTOR_CK(hipEventRecord(ctx->ev1, st), "recording an event");
+    if (profile)
+        RAPTOR_CK(launch_disk_profile(dI, dG, n, n_bins, g_lo, g_hi, p.dalpha * p.dbeta, dP, st),
+                  "launching the profile");
+    const hipMemcpyKind d2x = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (intensity && dI != intensity) RAPTOR_CK(hipMemcpyAsync(intensity, dI, n * 8, d2x, st), "copying images");
+    if (redshift && dG != redshift) RAPTOR_CK(hipMemcpyAsync(redshift, dG, n * 8, d2x, st), "copying images");
+    if (ray_status && dS != ray_status) RAPTOR_CK(hipMemcpyAsync(ray_status, dS, n * 4, d2x, st), "copying status");
+    if (ray_steps && dN != ray_steps) RAPTOR_CK(hipMemcpyAsync(ray_steps, dN, n * 4, d2x, st), "copying steps");
+    if (profile && dP != profile)
+        RAPTOR_CK(hipMemcpyAsync(profile, dP, (size_t)n_bins * 8, d2x, st), "copying the profile");
+    unsigned long long hs[ST_COUNT];
+    RAPTOR_CK(hipMemcpyAsync(hs, ctx->stats.p, sizeof hs, hipMemcpyDeviceToHost, st), "copying statistics");
+    RAPTOR_CK(hipStreamSynchronize(st), "running the disk test");
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->rays = (uint64_t)n;
+        stats->ray_steps = hs[0];
+        stats->samples = hs[1];
+        float ms = 0.0f;
+        RAPTOR_CK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "reading the kernel time");
+        stats->kernel_ms = ms;
+    }
+    return RAPTOR_OK;
+}
+
+raptor_status raptor_work_per_step(int32_t integrator, double* flops, double* special)
+{
+    if (integrator < RAPTOR_RK4 || integrator > RAPTOR_VERLET_CORRECTED) return RAPTOR_E_INVALID;
+    using C = rt::OpCounted;
+    C y[8] = {C(0.0), C(9.0), C(1.1), C(0.3), C(1.05), C(-0.9), C(0.02), C(0.01)};
+    C acc[4] = {C(0.01), C(-0.02), C(0.001), C(0.0001)};
+    rt::g_tally = rt::OpTally{};
+    const rk::Spin<C> sp = rk::make_spin(C(0.9375), C(1.0));
+    const C dl = -rk::step_size(C(0.05), y);
+    C s0, c0;
+    rt::sincos_(y[2], &s0, &c0);
+    if (integrator == RAPTOR_RK2)
+        rk::rk2_step(sp, y, dl, s0, c0);
+    else if (integrator == RAPTOR_RK4)
+        rk::rk4_step(sp, y, dl, s0, c0);
+    else
+        rk::verlet_step(sp, y, acc, dl, integrator == RAPTOR_VERLET_CORRECTED, s0, c0);
+    if (flops) *flops = rt::g_tally.flops;
+    if (special) *special = rt::g_tally.special;
     return RAPTOR_OK;
 }
 

@@ -215,6 +215,63 @@ __host__ __device__ inline void rk4_step(const Spin<T>& sp, T* y, T dl, T s0, T 
     }
 }
 
+// One second-order Runge-Kutta (midpoint) step: dk/dlambda at y and at y + (dl/2) f(y), then
+// y + dl f(midpoint).  The paper names RK2 for its timing runs without spelling it out; the
+// midpoint rule is the reading taken.
+template <class T>
+__host__ __device__ inline void rk2_step(const Spin<T>& sp, T* y, T dl, T s0, T c0)
+{
+    T t[8], dk[4];
+    T s, c;
+    ks_accel(sp, y, s0, c0, dk);
+    const T h2 = T(0.5) * dl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        t[i] = y[i] + h2 * y[4 + i];
+        t[4 + i] = y[4 + i] + h2 * dk[i];
+    }
+    sincos_shift(y[2], s0, c0, t[2], &s, &c);
+    ks_accel(sp, t, s, c, dk);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        y[i] = y[i] + dl * t[4 + i];
+        y[4 + i] = y[4 + i] + dl * dk[i];
+    }
+}
+
+// One velocity-Verlet step (Sec. 2.2.2) with A = dk/dlambda at y carried in acc:
+//   x' = x + k dl + A dl^2/2,  k_p = k + A dl,  A' = accel(x', k_p),  k' = k + (A + A') dl/2,
+// with the corrector A' = accel(x', k') and k' recomputed once more.  acc returns the last
+// evaluated derivative.  One connection evaluation per step (two with the corrector).
+template <class T>
+__host__ __device__ inline void verlet_step(const Spin<T>& sp, T* y, T* acc, T dl, bool corrector, T s0, T c0)
+{
+    T t[8], dk[4];
+    T s, c;
+    const T hh = T(0.5) * dl * dl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        t[i] = y[i] + y[4 + i] * dl + hh * acc[i];
+        t[4 + i] = y[4 + i] + acc[i] * dl;
+    }
+    sincos_shift(y[2], s0, c0, t[2], &s, &c);
+    ks_accel(sp, t, s, c, dk);
+    const T h2 = T(0.5) * dl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[4 + i] = y[4 + i] + h2 * (acc[i] + dk[i]);
+    if (corrector) {
+        ks_accel(sp, t, s, c, dk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[4 + i] = y[4 + i] + h2 * (acc[i] + dk[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        y[i] = t[i];
+        y[4 + i] = t[4 + i];
+        acc[i] = dk[i];
+    }
+}
+
 // Virtual camera (Sec. 2.3) at radius r_cam and polar angle incl, impact parameters
 // (alpha, beta): E = 1, L = -alpha sin(i), Q = beta^2 + cos^2(i)(alpha^2 - a^2),
 // k_theta = sign(beta) sqrt|Q - L^2 cot^2(i) + a^2 cos^2(i)|, k_r > 0 from the null

@@ -12,12 +12,18 @@ hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, in
 size_t flux_partials(int n_jobs, int max_nu);
 hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* part,
                        double* flux, int max_nu, hipStream_t st);
-hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int* vgprs, int* spill_bytes,
-                                   int* max_threads);
-// mlpc: the variant with the learned closure (always the uncapped register variant)
-const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = false);
+hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int integ, int* vgprs,
+                                   int* spill_bytes, int* max_threads);
+// mlpc: the variant with the learned closure; integ: INTEG_* (the second-order integrators have
+// the 2-waves-per-SIMD variant only)
+const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = false, int integ = INTEG_RK4);
 // dynamic LDS bytes of a trace-kernel work-group of `threads` lanes (mlpc: plus the staged network)
 size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc);
+
+// ---- thin disk (disk.hip)
+hipError_t launch_disk(const DiskParams& p, int blocks, hipStream_t st);
+hipError_t launch_disk_profile(const double* intensity, const double* redshift, long long n, int n_bins, double g_lo,
+                               double g_hi, double dA, double* profile, hipStream_t st);
 
 // ---- learned closure (mlp.hip)
 namespace mlp {

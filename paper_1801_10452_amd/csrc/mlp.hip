@@ -7,7 +7,7 @@
 //                    backward (BF16 MFMA) and the wave's partial parameter gradient
 //  reduce_kernel     fixed-order sum of the wave partials; Adam step on the FP32 parameters
 //                    and re-packing of the BF16 hi / lo copies -- or the plain gradient
-//  forward_kernel    batched inference (MFMA), one wave per 64 samples
+//  forward_kernel    batched inference from an LDS copy of the network (16x16x32 MFMA)
 //  forward_f32 / backward_f32   FP32 reference path (one thread per sample, no matrix cores)
 #include "launch.hpp"
 #include "mlp_device.hpp"
@@ -302,19 +302,25 @@ __global__ void reduce_kernel(const float* partial, int n_waves, int mode, float
     }
 }
 
+// Batched inference through the same LDS-staged path as the trace kernel: 256 samples per
+// work-group of four waves, one sample per lane.
 template <bool SPLIT>
-__global__ void __launch_bounds__(64) forward_kernel(Net net, const float* X, long long n, float* Y)
+__global__ void __launch_bounds__(256) forward_kernel(Net net, const float* X, long long n, float* Y)
 {
-    const long long i = 64ll * blockIdx.x + threadIdx.x;
+    extern __shared__ __align__(16) unsigned char lds[];
+    stage_weights(net, lds, threadIdx.x, blockDim.x);
+    __syncthreads();
+    const long long i = 256ll * blockIdx.x + threadIdx.x;
+    const bool active = i < n;
     float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-    if (i < n) {
+    if (active) {
         x0 = X[3 * i];
         x1 = X[3 * i + 1];
         x2 = X[3 * i + 2];
     }
     float y0, y1;
-    forward_wave<SPLIT>(net, x0, x1, x2, &y0, &y1);
-    if (i < n) {
+    forward_wave_lds<SPLIT>(lds, active, x0, x1, x2, &y0, &y1);
+    if (active) {
         Y[2 * i] = y0;
         Y[2 * i + 1] = y1;
     }
@@ -422,11 +428,11 @@ hipError_t mlp_launch_reduce(const float* partial, int n_waves, int mode, float*
 
 hipError_t mlp_launch_forward(const mlp::Net& net, bool split, const float* X, long long n, float* Y, hipStream_t st)
 {
-    const int blocks = (int)((n + 63) / 64);
+    const int blocks = (int)((n + 255) / 256);
     if (split)
-        hipLaunchKernelGGL(mlp::forward_kernel<true>, dim3(blocks), dim3(64), 0, st, net, X, n, Y);
+        hipLaunchKernelGGL(mlp::forward_kernel<true>, dim3(blocks), dim3(256), mlp::LDS_NET_BYTES, st, net, X, n, Y);
     else
-        hipLaunchKernelGGL(mlp::forward_kernel<false>, dim3(blocks), dim3(64), 0, st, net, X, n, Y);
+        hipLaunchKernelGGL(mlp::forward_kernel<false>, dim3(blocks), dim3(256), mlp::LDS_NET_BYTES, st, net, X, n, Y);
     return hipGetLastError();
 }
 

@@ -165,57 +165,141 @@ struct GlobalWeights {
     __device__ inline float out_bias(int o) const { return net.P[OFF_B5 + o]; }
 };
 
-// Weight source: a work-group's LDS copy in fragment order -- fragment f of lane l is the
-// 16-byte pair {hi, lo} at (64 f + l) * 16, so a lane's fragment is one conflict-free 128-bit
-// LDS read -- followed by the hidden biases [4][64] and the two output biases.
-constexpr int LDS_FRAG_BYTES = N_FRAGS * 64 * 16;
+// ---- inference from a work-group's LDS copy of the network ---------------------------------
+// Hidden and output layers use v_mfma_f32_16x16x32_bf16 (K = 32 per instruction, twice the
+// work of the 16x16x16 form at about the same issue cost on gfx950).  Its operands hold eight
+// K values per lane: A[m = l%16][k = 8(l/16) + j], B[k = 8(l/16) + j][n = l%16], j = 0..7,
+// with D laid out as in the 16x16x16 form.  Two D fragments of consecutive 16-row tiles p0 =
+// 2q, p1 = 2q + 1 concatenated per lane give rows 32q + 4(l/16) + {0..3} and
+// 32q + 16 + 4(l/16) + {0..3}: used directly as a K = 32 B fragment whose K slots are these
+// hidden units.  The staged A fragments take the same unit order, so the contraction is
+// unchanged and no data moves between lanes.
+//
+// LDS layout (bytes): layer 1, four 16x16x16 A fragments, lane l at f * 1024 + l * 16 as
+// {hi[4], lo[4]}; then 26 K = 32 fragments of 2048 bytes, lane l at +l * 32 as {hi[8], lo[8]}:
+// hidden layers 2..4 (index 8 (L - 1) + 2 mt + kq) and the output layer (index 24 + kq); then
+// the hidden biases [4][64] and the two output biases.
+constexpr int LDS_L1_BYTES = 4 * 64 * 16;
+constexpr int LDS_K32_BYTES = 64 * 32;
+constexpr int LDS_FRAG_BYTES = LDS_L1_BYTES + 26 * LDS_K32_BYTES;
 constexpr int LDS_NET_BYTES = LDS_FRAG_BYTES + (4 * 64 + 4) * 4;
+static_assert(LDS_FRAG_BYTES == N_FRAGS * 64 * 16, "fragment bytes");
 
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 
-template <bool SPLIT>
-struct LdsWeights {
-    const bf16x8* frag;
-    const float* b;
-    __device__ inline Split w(int layer, int mt, int kt, int lane) const
-    {
-        const bf16x8 v = frag[64 * frag_index(layer, mt, kt) + lane];
-        Split s;
-        s.hi = __builtin_shufflevector(v, v, 0, 1, 2, 3);
-        s.lo = SPLIT ? __builtin_shufflevector(v, v, 4, 5, 6, 7) : bf16x4{0, 0, 0, 0};
-        return s;
-    }
-    __device__ inline const float* bias(int layer) const { return b + 64 * layer; }
-    __device__ inline float out_bias(int o) const { return b[256 + o]; }
+struct Split8 {
+    bf16x8 hi, lo;
 };
 
-// Copy the network into LDS in the LdsWeights layout (all threads of the work-group take part;
-// the caller synchronises the work-group afterwards).
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c, 0,
+                                                   0, 0);
+}
+
+template <bool SPLIT>
+__device__ inline f32x4 mfma32_s(const Split8& a, const Split8& b, f32x4 c)
+{
+    if (SPLIT) {
+        c = mfma32(a.lo, b.hi, c);
+        c = mfma32(a.hi, b.lo, c);
+    }
+    return mfma32(a.hi, b.hi, c);
+}
+
+// B fragment of K pair q from the activations of tiles 2q and 2q + 1
+__device__ inline Split8 join(const Split& a, const Split& b)
+{
+    Split8 s;
+    s.hi = __builtin_shufflevector(a.hi, b.hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    s.lo = __builtin_shufflevector(a.lo, b.lo, 0, 1, 2, 3, 4, 5, 6, 7);
+    return s;
+}
+
+// Copy the network into LDS in the layout above (all threads of the work-group take part; the
+// caller synchronises the work-group afterwards).
 __device__ inline void stage_weights(const Net& net, unsigned char* lds, int tid, int nthreads)
 {
-    bf16x4* fr = reinterpret_cast<bf16x4*>(lds);
-    for (int s = tid; s < N_FRAGS * 64; s += nthreads) {
+    bf16x4* l1 = reinterpret_cast<bf16x4*>(lds);
+    for (int s = tid; s < 4 * 64; s += nthreads) {
         const int f = s >> 6, lane = s & 63;
-        int pw, stride = 64, m0 = 0, k0 = 0;
-        if (f < 4) {
-            pw = PW1;
-            stride = 16;
-            m0 = 16 * f;
-        } else if (f < 52) {
-            const int L = (f - 4) >> 4, r = (f - 4) & 15;
+        l1[2 * s] = frag_a(net.W + PW1, 16, 16 * f, 0, lane);
+        l1[2 * s + 1] = frag_a(net.Wlo + PW1, 16, 16 * f, 0, lane);
+    }
+    bf16x4* k32 = reinterpret_cast<bf16x4*>(lds + LDS_L1_BYTES);
+    for (int s = tid; s < 26 * 64; s += nthreads) {
+        const int idx = s >> 6, lane = s & 63;
+        int pw, m0 = 0, kq;
+        if (idx < 24) {
+            const int L = idx >> 3, r = idx & 7;
             pw = L == 0 ? PW2 : L == 1 ? PW3 : PW4;
-            m0 = 16 * (r >> 2);
-            k0 = 16 * (r & 3);
+            m0 = 16 * (r >> 1);
+            kq = r & 1;
         } else {
             pw = PW5;
-            k0 = 16 * (f - 52);
+            kq = idx - 24;
         }
-        fr[2 * s] = frag_a(net.W + pw, stride, m0, k0, lane);
-        fr[2 * s + 1] = frag_a(net.Wlo + pw, stride, m0, k0, lane);
+        const int ka = 32 * kq, kb = 32 * kq + 16;   // frag_a adds 4 (l / 16)
+        k32[4 * s] = frag_a(net.W + pw, 64, m0, ka, lane);
+        k32[4 * s + 1] = frag_a(net.W + pw, 64, m0, kb, lane);
+        k32[4 * s + 2] = frag_a(net.Wlo + pw, 64, m0, ka, lane);
+        k32[4 * s + 3] = frag_a(net.Wlo + pw, 64, m0, kb, lane);
     }
     float* b = reinterpret_cast<float*>(lds + LDS_FRAG_BYTES);
     for (int i = tid; i < 4 * 64 + 4; i += nthreads)
         b[i] = i < 256 ? net.P[hidden_bias_off(i >> 6) + (i & 63)] : (i < 258 ? net.P[OFF_B5 + i - 256] : 0.0f);
+}
+
+template <bool SPLIT>
+__device__ inline Split lds_w1(const unsigned char* lds, int f, int lane)
+{
+    const bf16x4* p = reinterpret_cast<const bf16x4*>(lds + f * 1024 + lane * 16);
+    Split s;
+    s.hi = p[0];
+    s.lo = SPLIT ? p[1] : bf16x4{0, 0, 0, 0};
+    return s;
+}
+
+template <bool SPLIT>
+__device__ inline Split8 lds_w32(const unsigned char* lds, int idx, int lane)
+{
+    const bf16x8* p = reinterpret_cast<const bf16x8*>(lds + LDS_L1_BYTES + idx * LDS_K32_BYTES + lane * 32);
+    Split8 s;
+    s.hi = p[0];
+    s.lo = SPLIT ? p[1] : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    return s;
+}
+
+// Forward pass of one 16-sample column block from the LDS copy (see forward_block).
+template <bool SPLIT>
+__device__ inline f32x4 forward_block_lds(const unsigned char* lds, const Split& bx, int lane)
+{
+    const float* bias = reinterpret_cast<const float*>(lds + LDS_FRAG_BYTES);
+    const int g4 = 4 * (lane >> 4);
+    Split h[4];
+    f32x4 acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = mfma_s<SPLIT>(lds_w1<SPLIT>(lds, mt, lane), bx, f32x4{0, 0, 0, 0});
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) h[mt] = activate<SPLIT>(acc[mt], bias + 16 * mt + g4);
+#pragma unroll
+    for (int L = 1; L < 4; ++L) {
+        const Split8 hb0 = join(h[0], h[1]), hb1 = join(h[2], h[3]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 a = mfma32_s<SPLIT>(lds_w32<SPLIT>(lds, 8 * (L - 1) + 2 * mt, lane), hb0, f32x4{0, 0, 0, 0});
+            acc[mt] = mfma32_s<SPLIT>(lds_w32<SPLIT>(lds, 8 * (L - 1) + 2 * mt + 1, lane), hb1, a);
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h[mt] = activate<SPLIT>(acc[mt], bias + 64 * L + 16 * mt + g4);
+    }
+    const Split8 hb0 = join(h[0], h[1]), hb1 = join(h[2], h[3]);
+    f32x4 o = mfma32_s<SPLIT>(lds_w32<SPLIT>(lds, 24, lane), hb0, f32x4{0, 0, 0, 0});
+    o = mfma32_s<SPLIT>(lds_w32<SPLIT>(lds, 25, lane), hb1, o);
+    o.x += bias[256];
+    o.y += bias[257];
+    return o;
 }
 
 // Forward pass of one 16-sample column block.  bx: input B fragment (lanes 0..15 hold the
@@ -280,25 +364,48 @@ __device__ inline Split input_block(float x0, float x1, float x2, int cb, int la
     return s;
 }
 
-// Forward pass of 64 samples, one per lane (all 64 lanes must call it together).  x0..x2 are
-// this lane's normalised inputs; returns this lane's standardised outputs.
-template <bool SPLIT, class WS>
-__device__ inline void forward_wave(const WS& ws, float x0, float x1, float x2, float* y0, float* y1)
+// Forward pass for the lanes with active set (all 64 lanes of the wave must call it together):
+// the active lanes' inputs are first packed to lanes 0..n-1 (a permutation through ds_permute),
+// only ceil(n / 16) column blocks are evaluated, and each active lane gets its own outputs
+// back.  Inactive lanes get zeros.
+template <bool SPLIT>
+__device__ inline void forward_wave_lds(const unsigned char* lds, bool active, float x0, float x1, float x2, float* y0,
+                                        float* y1)
 {
     const int lane = threadIdx.x & 63;
+    const unsigned long long mask = __ballot(active);
+    const int n = __popcll(mask);
+    *y0 = 0.0f;
+    *y1 = 0.0f;
+    if (n == 0) return;
+    const int r_in = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+    const unsigned long long inv = ~mask;
+    const int r_out = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(inv >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)inv, 0u));
+    const int dst = 4 * (active ? r_in : n + r_out);
+    const float c0 = __builtin_bit_cast(float, __builtin_amdgcn_ds_permute(dst, __builtin_bit_cast(int, x0)));
+    const float c1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_permute(dst, __builtin_bit_cast(int, x1)));
+    const float c2 = __builtin_bit_cast(float, __builtin_amdgcn_ds_permute(dst, __builtin_bit_cast(int, x2)));
     float r0 = 0.0f, r1 = 0.0f;
+    const int ncb = (n + 15) >> 4;
 #pragma unroll 1
-    for (int cb = 0; cb < 4; ++cb) {
-        const Split bx = input_block<SPLIT>(x0, x1, x2, cb, lane);
-        const f32x4 o = forward_block<SPLIT>(ws, bx, lane);
+    for (int cb = 0; cb < ncb; ++cb) {
+        // keep the fragment reads inside the loop: hoisting all 56 of them out of it would hold
+        // 224 registers for the whole pass, where re-reading LDS per column block is cheap
+        __asm__ volatile("" ::: "memory");
+        const Split bx = input_block<SPLIT>(c0, c1, c2, cb, lane);
+        const f32x4 o = forward_block_lds<SPLIT>(lds, bx, lane);
         const float v0 = __shfl(o.x, lane & 15, 64), v1 = __shfl(o.y, lane & 15, 64);
         if ((lane >> 4) == cb) {
             r0 = v0;
             r1 = v1;
         }
     }
-    *y0 = r0;
-    *y1 = r1;
+    // lane j < n holds the outputs of the j-th active lane
+    const float g0 = __shfl(r0, active ? r_in : 0, 64), g1 = __shfl(r1, active ? r_in : 0, 64);
+    if (active) {
+        *y0 = g0;
+        *y1 = g1;
+    }
 }
 
 // Normalised network inputs from the raw closure inputs.

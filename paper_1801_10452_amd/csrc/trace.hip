@@ -71,10 +71,13 @@ struct Transfer<double> {
     }
 };
 
-// FP32 transfer.  The coefficients j, alpha, S, the step's optical depth and contribution are
-// float; the arguments of the exponentials whose size amplifies rounding -- X^1/3 in the
-// emissivity (up to ~40) and ln K2 -- are formed in double and exponentiated by exp_mixed, so
-// every coefficient carries a few float ulps independent of the argument's size.
+// FP32 transfer.  The coefficients j, alpha, S and the step's contribution are float
+// mantissas; the arguments of the exponentials whose size amplifies rounding -- X^1/3 in the
+// emissivity (up to ~40 where the flux matters) and ln K2 -- are formed in double.  The
+// cut-off factor exp(-X^1/3) is split exactly into 2^-n 2^-f: the float arithmetic carries the
+// mantissa 2^-f and the power of two 2^-n is applied in double at the end, so emission far
+// below the float range (X^1/3 > 87, common at high frequencies) keeps its value instead of
+// flushing to zero.  The results (contribution and optical depth of the step) are doubles.
 template <>
 struct Transfer<float> {
     float ne, the, nu_s, k2_inv, ds, inr3;
@@ -99,28 +102,39 @@ struct Transfer<float> {
             k2_inv = (p.closure == CL_K2_PAPER) ? 1.0f / (2.0f * the * the)
                                                : rt::exp_mixed(-pl::ln_k2(p.k2, ::log(fl[1])));
     }
-    __device__ inline void contribution(const TraceParams& p, double nu_obs, float& A, float& dtau) const
+    __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
-        float j, al, S;
         if (p.closure == CL_CONST) {
-            j = (float)p.const_j;
-            al = (float)p.const_alpha;
-            S = al > 0.0f ? j / al : 0.0f;
-        } else if (emits) {
-            const double X = nu_obs * nr_inv_nus;
-            if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
-            const double tt = rt::cbrt_refined(X);
-            const float t = (float)tt;
-            const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
-            j = 1.1396857174835936e-29f * ne * nu_s * k2_inv * t * tc * tc * rt::exp_mixed(-tt);
-            const float nuf = (float)(nu_obs * nr);
-            const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
-            S = q * q * q / ::expm1f((float)pl::H_OVER_MEC2 * nuf / the);
-            al = j / S;
-        } else {
+            const float j = (float)p.const_j, al = (float)p.const_alpha;
+            float Af, dtf;
+            pl::step_source(j, al, al > 0.0f ? j / al : 0.0f, ds, inr3, Af, dtf);
+            A = Af;
+            dtau = dtf;
             return;
         }
-        pl::step_source(j, al, S, ds, inr3, A, dtau);
+        if (!emits) return;
+        const double X = nu_obs * nr_inv_nus;
+        if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
+        const double tt = rt::cbrt_refined(X);
+        // exp(-tt) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in double too
+        const double z = ::fmin(tt * 1.4426950408889634, 1100.0);
+        const double n = __builtin_rint(z);
+        const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
+        const double scale = __builtin_ldexp(1.0, -(int)n);
+        const float t = (float)tt;
+        const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
+        const float jm = 1.1396857174835936e-29f * ne * nu_s * k2_inv * t * tc * tc * em;   // j = jm 2^-n
+        const float nuf = (float)(nu_obs * nr);
+        const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
+        const float S = q * q * q / ::expm1f((float)pl::H_OVER_MEC2 * nuf / the);
+        const float dtm = jm / S * ds;                            // dtau = dtm 2^-n
+        dtau = (double)dtm * scale;
+        if (dtau > 1e-8) {
+            A = (double)(S * -::expm1f(-(float)dtau) * inr3);
+        } else {
+            // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): S dtau = j ds to float precision
+            A = (double)(jm * ds * inr3) * scale;
+        }
     }
 };
 
@@ -134,7 +148,7 @@ __device__ inline float attenuation<float>(double tau) { return rt::exp_mixed(-t
 
 // ---------------------------------------------------------------------------------------
 // Sample compaction.  A lane whose ray takes a step inside the plasma does not evaluate the
-// sample at once: it queues the point (ten doubles) in its wave's LDS area, up to QK per lane.
+// sample at once: it queues the point (ten doubles) in its wave's LDS area, up to K per lane.
 // When some lane's queue is full, or a ray with queued samples terminates, the wave evaluates
 // all queued samples together -- sample i of the flattened queue on lane i mod 64 -- so the
 // expensive part (MKS map, gather, fluid frame, closure) runs on full waves.  Each owner then
@@ -143,20 +157,29 @@ __device__ inline float attenuation<float>(double tau) { return rt::exp_mixed(-t
 // ---------------------------------------------------------------------------------------
 constexpr int N_FIELDS = 10;   // t, r, theta, phi, k^t, k^r, k^phi, |dlambda|, sin, cos
 
+// What the evaluation of a queued sample needs from its ray's job.
 struct LaneInfo {
     double a;
     int grid, fast_snap, nu_base, n_nu;
 };
 
+__device__ inline LaneInfo lane_info(const TraceParams& p, int job)
+{
+    const DevJob& J = p.jobs[job];
+    return LaneInfo{J.a, J.grid, J.fast_snap, J.nu_base, J.n_nu};
+}
+
 template <int NNU, class TT>
 struct Queue {
     // pending samples per lane: two while the LDS area stays within 32 KiB per wave
-    static constexpr int K = (64 * 2 * (N_FIELDS * 8 + 2 * NNU * (int)sizeof(TT) + 4) <= 32768) ? 2 : 1;
+    // (results are doubles in both precisions: an FP32 contribution carries its power-of-two
+    // scale, see Transfer<float>)
+    static constexpr int K = (64 * 2 * (N_FIELDS * 8 + 2 * NNU * 8 + 4) <= 32768) ? 2 : 1;
     static constexpr int SLOTS = 64 * K;
     static constexpr size_t FIELD_BYTES = (size_t)N_FIELDS * SLOTS * sizeof(double);
-    static constexpr size_t RES_BYTES = (size_t)2 * NNU * SLOTS * sizeof(TT);
+    static constexpr size_t RES_BYTES = (size_t)2 * NNU * SLOTS * sizeof(double);
     static constexpr size_t MAP_BYTES = (size_t)SLOTS * sizeof(int);
-    static constexpr size_t INFO_BYTES = 64 * sizeof(LaneInfo);
+    static constexpr size_t INFO_BYTES = 64 * sizeof(int);   // job index of each lane's ray
     static constexpr size_t PER_WAVE = (FIELD_BYTES + RES_BYTES + MAP_BYTES + INFO_BYTES + 15) / 16 * 16;
 };
 
@@ -170,7 +193,8 @@ __device__ inline void wave_lds_sync()
 // Evaluate one queued sample: fluid state, fluid frame, closure, and per frequency the
 // attenuation-free contribution A (observed units) and the optical depth dtau of the step.
 template <int NNU, class TT>
-__device__ inline bool eval_sample(const TraceParams& p, const double* q, const LaneInfo& li, TT* A, TT* dtau)
+__device__ inline bool eval_sample(const TraceParams& p, const double* q, const LaneInfo& li, double* A,
+                                   double* dtau)
 {
     const DevGrid& G = p.grids[li.grid];
     const double y[8] = {q[0], q[1], q[2], q[3], q[4], q[5], 0.0, q[6]};
@@ -182,8 +206,8 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
     tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
 #pragma unroll
     for (int f = 0; f < NNU; ++f) {
-        A[f] = TT(0);
-        dtau[f] = TT(0);
+        A[f] = 0.0;
+        dtau[f] = 0.0;
         if (f < li.n_nu) tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
     }
     return zamo;
@@ -194,7 +218,7 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
 // closure inputs leave the training box use the exact closure.
 template <int NNU, class TT>
 __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char* lds_net, bool has, const double* q,
-                                      const LaneInfo& li, TT* A, TT* dtau, unsigned long long& c_zamo,
+                                      const LaneInfo& li, double* A, double* dtau, unsigned long long& c_zamo,
                                       unsigned long long& c_fallback)
 {
     double fl[4] = {0.0, 1.0, 1.0, 0.0};
@@ -210,8 +234,6 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
         tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
     }
     c_zamo += __popcll(__ballot(zamo));
-    const mlp::bf16x8* frags = reinterpret_cast<const mlp::bf16x8*>(lds_net);
-    const float* biases = reinterpret_cast<const float*>(lds_net + mlp::LDS_FRAG_BYTES);
     const double nuc = pl::NUC_PER_GAUSS * fl[2];
     const float lth = (float)::log(fl[1] > 0.0 ? fl[1] : 1.0);
     const double ds = nr * q[7] * p.length_unit;
@@ -227,31 +249,36 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
                     x2 = inb ? mlp::norm_cb((float)cb) : 0.0f;
         float y0, y1;
         if (p.closure == CL_MLP_BF16)
-            mlp::forward_wave<false>(mlp::LdsWeights<false>{frags, biases}, x0, x1, x2, &y0, &y1);
+            mlp::forward_wave_lds<false>(lds_net, inb, x0, x1, x2, &y0, &y1);
         else
-            mlp::forward_wave<true>(mlp::LdsWeights<true>{frags, biases}, x0, x1, x2, &y0, &y1);
+            mlp::forward_wave_lds<true>(lds_net, inb, x0, x1, x2, &y0, &y1);
         if (!act) continue;
-        A[f] = TT(0);
-        dtau[f] = TT(0);
+        A[f] = 0.0;
+        dtau[f] = 0.0;
         if (inb) {
-            // the network gives ln j_hat + X^1/3 and ln alpha_hat + X^1/3 (standardised)
+            // the network gives ln j_hat + X^1/3 and ln alpha_hat + X^1/3 (standardised); the
+            // coefficients are formed in double from them (their logs span hundreds)
             const double sb2 = 1.0 - cb * cb;
             const double tc = rt::cbrt_refined(nu / ((2.0 / 9.0) * nuc * fl[1] * fl[1] * ::sqrt(sb2)));
-            const TT lnj = (TT)(y0 * mlp::SIGMA_J + mlp::MU_J - tc), lna = (TT)(y1 * mlp::SIGMA_A + mlp::MU_A - tc);
-            const TT ne = (TT)fl[0], nucT = (TT)nuc;
-            const TT j = ne * nucT * (TT)pl::J_PREF * rt::exp_(lnj);
-            const TT yy = (TT)(pl::H_OVER_MEC2 * nu / fl[1]);
-            const TT planck = (yy > TT(1e-4)) ? rt::expm1_(yy) / yy : TT(1) + TT(0.5) * yy;   // B_RJ / B_nu
-            const TT al = ne * (TT)pl::J_PREF / (TT(2.0 * pl::ME_CGS) * nucT) * rt::exp_(lna) * planck;
-            pl::step_source(j, al, j / al, (TT)ds, (TT)inr3, A[f], dtau[f]);
+            const double lnj = y0 * mlp::SIGMA_J + mlp::MU_J - tc, lna = y1 * mlp::SIGMA_A + mlp::MU_A - tc;
+            const double ne = fl[0];
+            const double j = ne * nuc * pl::J_PREF * ::exp(lnj);
+            const double yy = pl::H_OVER_MEC2 * nu / fl[1];
+            const double planck = (yy > 1e-4) ? ::expm1(yy) / yy : 1.0 + 0.5 * yy;   // B_RJ / B_nu
+            const double al = ne * pl::J_PREF / (2.0 * pl::ME_CGS * nuc) * ::exp(lna) * planck;
+            pl::step_source(j, al, j / al, ds, inr3, A[f], dtau[f]);
         } else if (tr.emits) {
             tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
         }
     }
 }
 
-template <int NNU, class TT, int WPE, bool MLPC>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, 256), amdgpu_waves_per_eu(WPE, 8)))
+// Work-groups of up to 256 lanes; up to 512 for the learned closure's 2-waves-per-SIMD variant,
+// whose eight waves share one LDS copy of the network (a 512-lane group caps a kernel at 256
+// registers per lane, which that variant fits anyway).
+template <int NNU, class TT, int WPE, bool MLPC, int INTEG>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, (MLPC && WPE >= 2) ? 512 : 256),
+                               amdgpu_waves_per_eu(WPE, 8)))
 trace_kernel(TraceParams p)
 {
     using Q = Queue<NNU, TT>;
@@ -260,9 +287,9 @@ trace_kernel(TraceParams p)
     const int lane = threadIdx.x & 63;
     unsigned char* wbase = smem + (size_t)(threadIdx.x >> 6) * Q::PER_WAVE;
     double* fields = reinterpret_cast<double*>(wbase);                                  // [N_FIELDS][SLOTS]
-    TT* res = reinterpret_cast<TT*>(wbase + Q::FIELD_BYTES);                            // [SLOTS][2*NNU]
+    double* res = reinterpret_cast<double*>(wbase + Q::FIELD_BYTES);                    // [SLOTS][2*NNU]
     int* slot_map = reinterpret_cast<int*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES);      // [SLOTS]
-    LaneInfo* info = reinterpret_cast<LaneInfo*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES + Q::MAP_BYTES);
+    int* lane_job = reinterpret_cast<int*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES + Q::MAP_BYTES);
     const double M = p.M;
     // learned closure: the work-group's copy of the network, after the queues of its waves
     unsigned char* lds_net = smem + (size_t)(blockDim.x >> 6) * Q::PER_WAVE;
@@ -272,10 +299,13 @@ trace_kernel(TraceParams p)
         __syncthreads();
     }
 
-    // ray state of this lane
+    // ray state of this lane (Verlet also carries dk/dlambda at y, valid when have_acc)
     double y[8];
+    double vacc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool have_acc = false;
     double a = 0.0, r_stop = 0.0, r_esc = 0.0, sth = 0.0, cth = 1.0;
     int job = 0, steps = 0, pix = 0, n_nu = 0, grid = 0, pending = 0;
+    int qstep[K];   // step number of each queued sample (the optical-depth cut-off ends the ray there)
     bool active = false;
     // accumulated intensity and optical depth in double (the per-sample terms are TT)
     double I[NNU], tau[NNU];
@@ -286,7 +316,7 @@ trace_kernel(TraceParams p)
 
     // wave-level statistics (ballot counts: scalar registers)
     unsigned long long c_rays = 0, c_steps = 0, c_samples = 0, c_hor = 0, c_esc = 0, c_max = 0, c_pole = 0,
-                       c_num = 0, c_zamo = 0, c_fallback = 0;
+                       c_num = 0, c_zamo = 0, c_fallback = 0, c_opq = 0;
 
     long long next = 0, end = 0;   // rays of the current tile not yet handed out (wave-uniform)
     bool drained = false;
@@ -333,8 +363,9 @@ trace_kernel(TraceParams p)
                         pix = py * J.nx + px;
                         n_nu = J.n_nu;
                         grid = J.grid;
-                        info[lane] = LaneInfo{a, J.grid, J.fast_snap, J.nu_base, J.n_nu};
+                        lane_job[lane] = job;
                         steps = 0;
+                        have_acc = false;
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) { I[f] = 0.0; tau[f] = 0.0; }
                         active = true;
@@ -355,7 +386,15 @@ trace_kernel(TraceParams p)
         if (active) {
             const rk::Spin<double> sp = rk::make_spin(a, M);
             const double dl = -rk::step_size(p.eps, y);
-            rk::rk4_step(sp, y, dl, sth, cth);
+            if (INTEG == INTEG_RK2) {
+                rk::rk2_step(sp, y, dl, sth, cth);
+            } else if (INTEG == INTEG_VERLET) {
+                if (!have_acc) rk::ks_accel(sp, y, sth, cth, vacc);
+                rk::verlet_step(sp, y, vacc, dl, p.integrator == INTEG_VERLET_CORR, sth, cth);
+                have_acc = true;
+            } else {
+                rk::rk4_step(sp, y, dl, sth, cth);
+            }
             ++steps;
             bool fin = true;
 #pragma unroll
@@ -364,6 +403,7 @@ trace_kernel(TraceParams p)
                 status = RAY_NUMERIC;
             } else {
                 reflected = rk::reflect_pole(y);
+                if (reflected) have_acc = false;   // the carried derivative belongs to the old chart
                 rt::sincos_small(y[2], &sth, &cth);
                 if (y[1] < r_stop)
                     status = RAY_HORIZON;
@@ -385,6 +425,9 @@ trace_kernel(TraceParams p)
                 fields[7 * Q::SLOTS + s] = -dl;
                 fields[8 * Q::SLOTS + s] = sth;
                 fields[9 * Q::SLOTS + s] = cth;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k == pending) qstep[k] = steps;
                 ++pending;
             }
         }
@@ -414,8 +457,9 @@ trace_kernel(TraceParams p)
                     double q[N_FIELDS];
 #pragma unroll
                     for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * Q::SLOTS + s] : 1.0;
-                    TT A[NNU], dt[NNU];
-                    eval_round_mlp<NNU, TT>(p, lds_net, has, q, info[s / K], A, dt, c_zamo, c_fallback);
+                    double A[NNU], dt[NNU];
+                    eval_round_mlp<NNU, TT>(p, lds_net, has, q, lane_info(p, lane_job[s / K]), A, dt, c_zamo,
+                                            c_fallback);
                     if (has) {
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
@@ -430,8 +474,8 @@ trace_kernel(TraceParams p)
                         double q[N_FIELDS];
 #pragma unroll
                         for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
-                        TT A[NNU], dt[NNU];
-                        zamo = eval_sample<NNU, TT>(p, q, info[s / K], A, dt);
+                        double A[NNU], dt[NNU];
+                        zamo = eval_sample<NNU, TT>(p, q, lane_info(p, lane_job[s / K]), A, dt);
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
                             res[s * 2 * NNU + f] = A[f];
@@ -443,16 +487,27 @@ trace_kernel(TraceParams p)
             }
             c_samples += total;
             wave_lds_sync();
-            // each owner folds its samples in order: I += exp(-tau) A, tau += dtau
+            // each owner folds its samples in order: I += exp(-tau) A, tau += dtau; with the
+            // optical-depth cut-off the ray ends after the first sample that makes it opaque at
+            // every frequency, and its later queued samples are dropped
+            bool cut = false;
+#pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (k < pending) {
+                if (k < pending && !cut) {
                     const int s = lane * K + k;
+                    double tmin = 1e300;
 #pragma unroll
                     for (int f = 0; f < NNU; ++f) {
                         if (f < n_nu) {
-                            I[f] = I[f] + (double)(attenuation<TT>(tau[f]) * res[s * 2 * NNU + f]);
-                            tau[f] = tau[f] + (double)res[s * 2 * NNU + NNU + f];
+                            I[f] = I[f] + (double)attenuation<TT>(tau[f]) * res[s * 2 * NNU + f];
+                            tau[f] = tau[f] + res[s * 2 * NNU + NNU + f];
+                            tmin = ::fmin(tmin, tau[f]);
                         }
+                    }
+                    if (p.tau_cutoff > 0.0 && tmin >= p.tau_cutoff) {
+                        cut = true;
+                        status = RAY_OPAQUE;
+                        steps = qstep[k];
                     }
                 }
             }
@@ -479,13 +534,14 @@ trace_kernel(TraceParams p)
             c_esc += __popcll(__ballot(status == RAY_ESCAPED));
             c_max += __popcll(__ballot(status == RAY_MAXSTEP));
             c_num += __popcll(__ballot(status == RAY_NUMERIC));
+            c_opq += __popcll(__ballot(status == RAY_OPAQUE));
         }
     }
 
     // ------------------------------------------------------------ statistics, one atomic per counter per wave
     if (lane == 0) {
         const unsigned long long st[ST_COUNT] = {c_rays, c_steps, c_samples, c_hor, c_esc, c_max, c_pole, c_num,
-                                                 c_fallback, c_zamo};
+                                                 c_fallback, c_zamo, c_opq};
 #pragma unroll
         for (int i = 0; i < ST_COUNT; ++i)
             if (st[i]) atomicAdd(p.stats + i, st[i]);
@@ -540,22 +596,30 @@ __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* sta
     if (threadIdx.x < ST_COUNT) stats[threadIdx.x] = 0ull;
 }
 
+// Instantiations: RK4 with every register budget (1, 2 or 3 waves per SIMD) and the learned
+// closure (1 or 2); the second-order integrators with the 2-waves-per-SIMD budget only.
 template <int NNU, class TT>
-const void* symbol_of(int wpe, bool mlpc)
+const void* symbol_of(int wpe, bool mlpc, int integ)
 {
-    if (mlpc) return (const void*)trace_kernel<NNU, TT, 1, true>;
-    return wpe >= 3 ? (const void*)trace_kernel<NNU, TT, 3, false>
-         : wpe == 2 ? (const void*)trace_kernel<NNU, TT, 2, false> : (const void*)trace_kernel<NNU, TT, 1, false>;
+    if (integ == INTEG_RK2) return (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK2>;
+    if (integ == INTEG_VERLET || integ == INTEG_VERLET_CORR)
+        return (const void*)trace_kernel<NNU, TT, 2, false, INTEG_VERLET>;
+    if (mlpc)
+        return wpe >= 2 ? (const void*)trace_kernel<NNU, TT, 2, true, INTEG_RK4>
+                        : (const void*)trace_kernel<NNU, TT, 1, true, INTEG_RK4>;
+    return wpe >= 3 ? (const void*)trace_kernel<NNU, TT, 3, false, INTEG_RK4>
+         : wpe == 2 ? (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK4>
+                    : (const void*)trace_kernel<NNU, TT, 1, false, INTEG_RK4>;
 }
 
 template <class TT>
-const void* symbol_tt(int max_nu, int wpe, bool mlpc)
+const void* symbol_tt(int max_nu, int wpe, bool mlpc, int integ)
 {
-    if (max_nu <= 1) return symbol_of<1, TT>(wpe, mlpc);
-    if (max_nu <= 4) return symbol_of<4, TT>(wpe, mlpc);
-    if (max_nu <= 8) return symbol_of<8, TT>(wpe, mlpc);
-    if (max_nu <= 16) return symbol_of<16, TT>(wpe, mlpc);
-    return symbol_of<32, TT>(wpe, mlpc);
+    if (max_nu <= 1) return symbol_of<1, TT>(wpe, mlpc, integ);
+    if (max_nu <= 4) return symbol_of<4, TT>(wpe, mlpc, integ);
+    if (max_nu <= 8) return symbol_of<8, TT>(wpe, mlpc, integ);
+    if (max_nu <= 16) return symbol_of<16, TT>(wpe, mlpc, integ);
+    return symbol_of<32, TT>(wpe, mlpc, integ);
 }
 
 }  // namespace
@@ -568,7 +632,7 @@ hipError_t launch_reset(unsigned int* tile_counter, unsigned long long* stats, h
 
 hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, int blocks, int threads, hipStream_t st)
 {
-    const void* fn = trace_kernel_symbol(max_nu, fp32, wpe, p.closure >= CL_MLP);
+    const void* fn = trace_kernel_symbol(max_nu, fp32, wpe, p.closure >= CL_MLP, p.integrator);
     void* args[] = {const_cast<TraceParams*>(&p)};
     return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args,
                            trace_kernel_lds(max_nu, fp32, threads, p.closure >= CL_MLP), st);
@@ -603,16 +667,16 @@ size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc)
     return waves * (fp32 ? per(0.0f) : per(0.0)) + (mlpc ? (size_t)mlp::LDS_NET_BYTES : 0);
 }
 
-const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc)
+const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc, int integ)
 {
-    return fp32 ? symbol_tt<float>(max_nu, wpe, mlpc) : symbol_tt<double>(max_nu, wpe, mlpc);
+    return fp32 ? symbol_tt<float>(max_nu, wpe, mlpc, integ) : symbol_tt<double>(max_nu, wpe, mlpc, integ);
 }
 
-hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int* vgprs, int* spill_bytes,
-                                   int* max_threads)
+hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int integ, int* vgprs,
+                                   int* spill_bytes, int* max_threads)
 {
     hipFuncAttributes at;
-    const hipError_t e = hipFuncGetAttributes(&at, trace_kernel_symbol(max_nu, fp32, wpe, mlpc));
+    const hipError_t e = hipFuncGetAttributes(&at, trace_kernel_symbol(max_nu, fp32, wpe, mlpc, integ));
     if (e != hipSuccess) return e;
     if (vgprs) *vgprs = at.numRegs;
     if (spill_bytes) *spill_bytes = (int)at.localSizeBytes;

@@ -20,6 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 CLOSURE_EXACT, CLOSURE_K2_PAPER, CLOSURE_CONST, CLOSURE_MLP, CLOSURE_MLP_BF16 = 0, 1, 2, 3, 4
 MLP_SPLIT, MLP_BF16, MLP_F32 = 0, 1, 2
 LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
+RK4, RK2, VERLET, VERLET_CORRECTED = 0, 1, 2, 3
 MLP_PARAMS = 12866
 RAY_HORIZON, RAY_ESCAPED, RAY_MAXSTEP, RAY_NUMERIC = 1, 2, 3, 4
 MAX_NU = 32
@@ -50,14 +51,15 @@ class COpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("r_stop_factor", C.c_double), ("max_steps", C.c_int32),
                 ("transfer_prec", C.c_int32), ("closure", C.c_int32), ("slow_light", C.c_int32), ("mem", C.c_int32),
                 ("launch", C.c_int32), ("mass_msun", C.c_double), ("dist_pc", C.c_double),
-                ("const_j", C.c_double), ("const_alpha", C.c_double), ("metric_mass", C.c_double)]
+                ("const_j", C.c_double), ("const_alpha", C.c_double), ("metric_mass", C.c_double),
+                ("integrator", C.c_int32), ("reserved", C.c_int32), ("tau_cutoff", C.c_double)]
 
 
 class CStats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("ray_steps", C.c_uint64), ("samples", C.c_uint64),
                 ("n_horizon", C.c_uint64), ("n_escaped", C.c_uint64), ("n_maxstep", C.c_uint64),
                 ("n_pole", C.c_uint64), ("n_numeric", C.c_uint64), ("n_mlp_fallback", C.c_uint64),
-                ("n_zamo_fallback", C.c_uint64), ("kernel_ms", C.c_double)]
+                ("n_zamo_fallback", C.c_uint64), ("kernel_ms", C.c_double), ("n_opaque", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,7 +92,8 @@ class CMlpReport(C.Structure):
 # every symbol include/raptor.h declares
 EXPORTS = ["raptor_create", "raptor_destroy", "raptor_last_error", "raptor_grid_upload", "raptor_grid_release",
            "raptor_default_opts", "raptor_trace_image", "raptor_trace_spectrum", "raptor_trace_spectrum_ex",
-           "raptor_trace_batch", "raptor_work_per_unit", "raptor_get_plan", "raptor_set_plan",
+           "raptor_trace_batch", "raptor_work_per_unit", "raptor_work_per_step", "raptor_get_plan", "raptor_set_plan",
+           "raptor_isco", "raptor_trace_disk",
            "raptor_autotune_batch", "raptor_kernel_info", "raptor_mlp_default_cfg", "raptor_mlp_init",
            "raptor_mlp_train", "raptor_mlp_get_params", "raptor_mlp_set_params", "raptor_mlp_get_weights",
            "raptor_mlp_set_weights", "raptor_mlp_forward", "raptor_mlp_backward", "raptor_mlp_closure"]
@@ -132,11 +135,15 @@ def lib():
         L.raptor_trace_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
                                          C.c_int32, V, V, C.POINTER(CStats)]
         L.raptor_work_per_unit.argtypes = [DP] * 6
-        L.raptor_get_plan.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan)]
-        L.raptor_set_plan.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan)]
+        L.raptor_work_per_step.argtypes = [C.c_int32, DP, DP]
+        L.raptor_isco.argtypes = [C.c_double, DP]
+        L.raptor_trace_disk.argtypes = [V, C.POINTER(CCamera), C.POINTER(COpts), C.c_double, C.c_int32, C.c_double,
+                                        C.c_double, V, V, V, V, V, C.POINTER(CStats)]
+        L.raptor_get_plan.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, C.POINTER(CPlan)]
+        L.raptor_set_plan.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, C.POINTER(CPlan)]
         L.raptor_autotune_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
                                             C.c_int32, C.c_int32, C.POINTER(CPlan), DP]
-        L.raptor_kernel_info.argtypes = [V, C.c_int32, C.c_int32, C.POINTER(CPlan), IP, IP, IP]
+        L.raptor_kernel_info.argtypes = [V, C.c_int32, C.c_int32, C.c_int32, C.POINTER(CPlan), IP, IP, IP]
         FP = C.POINTER(C.c_float)
         L.raptor_mlp_default_cfg.argtypes = [C.POINTER(CMlpCfg)]
         L.raptor_mlp_init.argtypes = [V, C.c_uint64]
@@ -182,6 +189,23 @@ def kernel_build_id():
         with open(os.path.join(PKG, "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
+
+
+def isco(spin):
+    v = C.c_double()
+    st = lib().raptor_isco(spin, C.byref(v))
+    if st != 0:
+        raise RaptorError(st, "spin out of range")
+    return v.value
+
+
+def work_per_step(integrator=RK4):
+    """(FP64 flops, special ops) of one accepted step of the integrator."""
+    v = [C.c_double() for _ in range(2)]
+    st = lib().raptor_work_per_step(integrator, C.byref(v[0]), C.byref(v[1]))
+    if st != 0:
+        raise RaptorError(st, "bad integrator")
+    return v[0].value, v[1].value
 
 
 def work_per_unit():
@@ -280,6 +304,25 @@ class Context:
                                              _ptr(image), _ptr(flux), C.byref(st)))
         return image, flux, st
 
+    def trace_disk(self, cam, opts=None, r_disk_out=15.0, n_bins=256, g_lo=0.0, g_hi=2.0, intensity=None,
+                   redshift=None, profile=None, ray_status=None, ray_steps=None):
+        """Thin-disk line test.  Returns (intensity [ny][nx], redshift [ny][nx], profile [n_bins],
+        stats); in host mode arrays are allocated here when not given."""
+        opts = opts or default_opts()
+        if opts.mem == MEM_HOST:
+            if intensity is None:
+                intensity = np.zeros((cam.ny, cam.nx))
+            if redshift is None:
+                redshift = np.zeros((cam.ny, cam.nx))
+            if profile is None and n_bins > 0:
+                profile = np.zeros(n_bins)
+        st = CStats()
+        c = make_camera(cam)
+        self._check(lib().raptor_trace_disk(self.h, C.byref(c), C.byref(opts), r_disk_out, n_bins, g_lo, g_hi,
+                                            _ptr(intensity), _ptr(redshift), _ptr(profile), _ptr(ray_status),
+                                            _ptr(ray_steps), C.byref(st)))
+        return intensity, redshift, profile, st
+
     def trace_batch(self, cams, grids, nu, opts=None, images=None, flux=None):
         """cams: list of cameras; grids: one GridHandle per camera; nu: [n_cams][n_nu] (or one
         list used for every camera).  images: all images concatenated, flux [n_cams][n_nu]."""
@@ -319,14 +362,14 @@ def _batch_args(cams, grids, nu):
     return n, nu, carr, garr
 
 
-def get_plan(ctx, n_nu, prec):
+def get_plan(ctx, n_nu, prec, closure=CLOSURE_EXACT):
     pl = CPlan()
-    ctx._check(lib().raptor_get_plan(ctx.h, n_nu, prec, C.byref(pl)))
+    ctx._check(lib().raptor_get_plan(ctx.h, n_nu, prec, closure, C.byref(pl)))
     return pl
 
 
-def set_plan(ctx, n_nu, prec, plan):
-    ctx._check(lib().raptor_set_plan(ctx.h, n_nu, prec, C.byref(plan)))
+def set_plan(ctx, n_nu, prec, plan, closure=CLOSURE_EXACT):
+    ctx._check(lib().raptor_set_plan(ctx.h, n_nu, prec, closure, C.byref(plan)))
 
 
 def autotune_batch(ctx, cams, grids, nu, opts=None, reps=2):
@@ -340,9 +383,9 @@ def autotune_batch(ctx, cams, grids, nu, opts=None, reps=2):
     return best, ms.value
 
 
-def kernel_info(ctx, n_nu, prec, plan):
+def kernel_info(ctx, n_nu, prec, plan, closure=CLOSURE_EXACT):
     v = [C.c_int32() for _ in range(3)]
-    ctx._check(lib().raptor_kernel_info(ctx.h, n_nu, prec, C.byref(plan), *[C.byref(x) for x in v]))
+    ctx._check(lib().raptor_kernel_info(ctx.h, n_nu, prec, closure, C.byref(plan), *[C.byref(x) for x in v]))
     return {"vgprs": v[0].value, "scratch_bytes": v[1].value, "blocks_per_cu": v[2].value}
 
 

@@ -165,3 +165,77 @@ def test_mlp_backward_central_differences(orc):
         p2[idx] -= h
         fd = ((orc.mlp_forward(p1, x) - orc.mlp_forward(p2, x)) * dy).sum() / (2 * h)
         assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-9)
+
+
+def test_tau_cutoff_on_a_uniform_shell(orc):
+    """Optical-depth cut-off (Sec. 3.1, backward scheme) on the uniform shell: the ray stops at
+    the first step where tau >= tau_c, reports OPAQUE, takes fewer steps, and by the telescoping
+    identity I = S (1 - exp(-tau_stop)) with tau_c <= tau_stop < tau_c + (last step's dtau); the
+    intensity lost against the full ray is at most S exp(-tau_c)."""
+    cam = S.Camera(spin=0.0, incl_deg=55.0, nx=2, ny=2)
+    j0, a0 = 2e-20, 0.5          # optical depth ~5 across the shell
+    gh, opts, Lu = slab_setup(orc, j0, a0, 0.01)
+    full, info_f, _ = orc.trace_ray(cam, gh, opts, 3.0, 2.0, [230e9])
+    tau_c = math.log(20.0)
+    opts.tau_cutoff = tau_c
+    cut, info_c, rec = orc.trace_ray(cam, gh, opts, 3.0, 2.0, [230e9], record=100000)
+    assert info_f.status == orc.ESCAPED and info_c.status == orc.OPAQUE
+    assert info_c.steps < info_f.steps
+    S_ = j0 / (a0 / Lu)
+    taus = np.cumsum([r.alpha * r.ds for r in rec[: info_c.steps] if r.sampled])
+    assert taus[-1] >= tau_c > taus[-2]
+    assert cut[0] == pytest.approx(S_ * -math.expm1(-taus[-1]), rel=1e-13)
+    assert 0.0 <= full[0] - cut[0] <= S_ * math.exp(-tau_c)
+
+
+def test_tau_cutoff_truncates_the_same_sum(orc):
+    """On the synthetic torus at 1 GHz (partly opaque): the cut ray's intensity is the full
+    ray's backward sum truncated at the first step with tau >= tau_c, and the emission lost
+    beyond it is at most exp(-tau_c) times its unattenuated sum."""
+    cam, g, nu = S.small_image()
+    gh = orc.GridHandle(g)
+    tau_c = math.log(1000.0)
+    opts = orc.make_opts()
+    n_opaque = 0
+    for px, py in [(32, 32), (30, 36), (40, 28), (25, 33), (36, 40)]:
+        al, be = orc.pixel_alpha_beta(cam, px, py)
+        full, info_f, rec = orc.trace_ray(cam, gh, opts, al, be, [1e9], record=20000)
+        opts_c = orc.make_opts(tau_cutoff=tau_c)
+        cut, info_c, _ = orc.trace_ray(cam, gh, opts_c, al, be, [1e9])
+        I, tau, k_stop, lost_bound = 0.0, 0.0, None, 0.0
+        for k, r in enumerate(rec[: info_f.steps]):
+            if not r.sampled:
+                continue
+            dtau = r.alpha * r.ds
+            A = (r.j / r.alpha) * -math.expm1(-dtau) / r.nu_r ** 3 if dtau > 0 else r.j * r.ds / r.nu_r ** 3
+            if k_stop is None:
+                I += math.exp(-tau) * A
+                tau += dtau
+                if tau >= tau_c:
+                    k_stop = k
+            else:
+                lost_bound += A
+        if k_stop is None:
+            assert info_c.status == info_f.status and cut[0] == full[0]
+            continue
+        n_opaque += 1
+        assert info_c.status == orc.OPAQUE and info_c.steps == k_stop + 1
+        assert cut[0] == pytest.approx(I, rel=1e-13)
+        assert 0.0 <= full[0] - cut[0] <= math.exp(-tau_c) * lost_bound * (1 + 1e-12)
+    assert n_opaque >= 2
+
+
+def test_tau_cutoff_needs_every_frequency_opaque(orc):
+    """With two frequencies a ray stops only once it is opaque at both: the rays the pair stops
+    are those both single-frequency runs stop, after the later of their two step counts."""
+    cam, g, nu = S.small_image()
+    gh = orc.GridHandle(g)
+    o1 = orc.make_opts(tau_cutoff=math.log(1000.0))
+    pix = np.arange(0, cam.nx * cam.ny, 7, dtype=np.int64)
+    _, st_a = orc.trace_pixels(cam, gh, o1, [1e8], pix)
+    _, st_b = orc.trace_pixels(cam, gh, o1, [1e9], pix)
+    _, st_ab = orc.trace_pixels(cam, gh, o1, [1e8, 1e9], pix)
+    both = (st_a[:, 0] == orc.OPAQUE) & (st_b[:, 0] == orc.OPAQUE)
+    assert both.sum() > 10 and ((st_a[:, 0] == orc.OPAQUE) & ~both).sum() > 10
+    assert np.array_equal(st_ab[:, 0] == orc.OPAQUE, both)
+    assert np.array_equal(st_ab[both, 1], np.maximum(st_a[both, 1], st_b[both, 1]))
