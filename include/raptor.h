@@ -238,7 +238,7 @@ enum { RAPTOR_MLP_PARAMS = 12866 };
 typedef struct {
     int64_t n_train;             /* training samples generated on the device (default 1e7) */
     int64_t n_val;               /* validation samples (default 1e5) */
-    int32_t epochs;              /* passes over the training samples (default 60) */
+    int32_t epochs;              /* passes over the training samples (default 120) */
     int32_t batch;               /* samples per Adam step, a multiple of 64 (default 4096) */
     float lr, lr_final;          /* Adam step size, cosine-decayed from lr to lr_final */
     float beta1, beta2, adam_eps, weight_decay;

@@ -73,7 +73,7 @@ struct MlpState {
 struct raptor_grid {
     DevGrid d{};
     void* cells = nullptr;
-    float* x2tab = nullptr;
+    float2* x2tab = nullptr;
     raptor_ctx* owner = nullptr;
 };
 

@@ -7,9 +7,9 @@
 // {n_e, Theta_e, B, Omega}.
 struct DevGrid {
     const void* cells;
-    const float* x2tab;        // x2(theta) at x2n uniform theta nodes on [0, pi] (start values)
+    const float2* x2tab;       // {x2, dx2/dtheta} at x2n uniform theta nodes on [0, pi] (start values)
     int x2n, pad;
-    double x2_inv_dth;
+    double x2_inv_dth, x2_dth;
     int n1, n2, n_snap, is_f64;
     double lnr_in, inv_d1, r_in, r_out, hslope, a_gen, t0, dt_snap, inv_dt, mod_amp;
     double mod_cos[4], mod_sin[4];   // cos / sin of the modulation phases

@@ -46,12 +46,17 @@ constexpr float MU_J = 4.0f, SIGMA_J = 6.0f, MU_A = -6.5f, SIGMA_A = 9.0f;
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// float -> bf16 bits, round to nearest even (finite inputs)
+// float -> bf16 bits, round to nearest even (finite inputs): the gfx950 conversion instruction
+// on the device, the same rounding in integer arithmetic on the host
 __host__ __device__ inline unsigned short f2bf(float f)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
+#else
     unsigned int u = __builtin_bit_cast(unsigned int, f);
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (unsigned short)(u >> 16);
+#endif
 }
 __host__ __device__ inline float bf2f(unsigned short b) { return __builtin_bit_cast(float, (unsigned int)b << 16); }
 
@@ -79,10 +84,12 @@ __device__ inline Split split4(float a, float b, float c, float d)
     return s;
 }
 
-__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware exp2 and reciprocal (about one ulp each)
+__device__ inline float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigmoid(z); }
 __device__ inline float silu_grad(float z)
 {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 

@@ -113,7 +113,7 @@ raptor_status raptor_mlp_default_cfg(raptor_mlp_train_cfg* c)
     std::memset(c, 0, sizeof *c);
     c->n_train = 10000000;
     c->n_val = 100000;
-    c->epochs = 60;
+    c->epochs = 120;
     c->batch = 4096;
     c->lr = 3e-3f;
     c->lr_final = 2e-5f;

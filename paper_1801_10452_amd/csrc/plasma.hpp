@@ -31,7 +31,7 @@ __host__ __device__ inline T mks_x2(T h, T th, T x0)
     const T hh = T(0.5) * (T(1.0) - h);
     for (int n = 0; n < 50; ++n) {
         T s, c;
-        sincospi_(T(2.0) * x, &s, &c);
+        sincos_small(T(2.0 * PI_D) * x, &s, &c);   // x in [0, 1]: argument in [0, 2 pi]
         const T f = T(PI_D) * x + hh * s - th;
         const T fp = T(PI_D) * (T(1.0) + (T(1.0) - h) * c);
         const T fpp = T(-2.0 * PI_D * PI_D) * (T(1.0) - h) * s;
@@ -40,7 +40,7 @@ __host__ __device__ inline T mks_x2(T h, T th, T x0)
             xn = T(0.05);
         } else {
             const T den = T(2.0) * fp * fp - f * fpp;
-            xn = (den > fp * fp * T(0.5)) ? x - T(2.0) * f * fp / den : x - f / fp;
+            xn = (den > fp * fp * T(0.5)) ? x - T(2.0) * f * fp * rcp_nr(den) : x - f * rcp_nr(fp);
             if (xn < T(0.0) || xn > T(1.0)) xn = T(0.05);
         }
         const T dx = fabs_(xn - x);
@@ -109,13 +109,17 @@ __device__ inline double modulation(const DevGrid& g, double r, double ph, doubl
     return 1.0 + g.mod_amp * acc;
 }
 
-// Start value of the MKS inverse: linear interpolation in the grid's x2(theta) table.
+// Start value of the MKS inverse: cubic Hermite interpolation in the grid's {x2, dx2/dtheta} table.
 __device__ inline double x2_start(const DevGrid& g, double th)
 {
     double q = ::fmin(::fmax(th * g.x2_inv_dth, 0.0), (double)(g.x2n - 1) - 1e-9);
     const int i = (int)q;
-    const double w = q - i;
-    return (1.0 - w) * g.x2tab[i] + w * g.x2tab[i + 1];
+    const double s = q - i;
+    const float2 A = g.x2tab[i], B = g.x2tab[i + 1];
+    const double s2 = s * s, s3 = s2 * s;
+    const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
+    const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
+    return h00 * A.x + h10 * A.y * g.x2_dth + h01 * B.x + h11 * B.y * g.x2_dth;
 }
 
 __device__ inline bool in_plasma(const DevGrid& g, double r) { return r >= g.r_in && r <= g.r_out; }

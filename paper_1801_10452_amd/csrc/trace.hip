@@ -13,6 +13,8 @@
 #include "launch.hpp"
 #include "mlp_device.hpp"
 
+#include <type_traits>
+
 namespace {
 
 __device__ inline int find_job(const DevJob* jobs, int n_jobs, long long tile)
@@ -49,7 +51,7 @@ struct Transfer<double> {
         ds = dsv;
         inr3 = rt::rcp_nr(nr * nr * nr);
         const double s2 = 1.0 - cosb * cosb;
-        sinb = s2 > 0.0 ? ::sqrt(s2) : 0.0;
+        sinb = s2 > 0.0 ? s2 * rt::rsqrt_nr(s2) : 0.0;
         emits = (ne > 0.0 && the > 0.0 && bf > 0.0 && sinb > 0.0);
         k2_inv = 0.0;
         if (emits && p.closure != CL_CONST)
@@ -92,7 +94,7 @@ struct Transfer<float> {
         ds = (float)dsv;
         inr3 = (float)rt::rcp_nr(nr_ * nr_ * nr_);
         const double s2 = 1.0 - cosb * cosb;
-        const double sb = s2 > 0.0 ? ::sqrt(s2) : 0.0;
+        const double sb = s2 > 0.0 ? s2 * rt::rsqrt_nr(s2) : 0.0;
         emits = (fl[0] > 0.0 && fl[1] > 0.0 && fl[2] > 0.0 && sb > 0.0);
         const double nus = (2.0 / 9.0) * pl::NUC_PER_GAUSS * fl[2] * fl[1] * fl[1] * sb;
         nu_s = (float)nus;
@@ -149,10 +151,12 @@ __device__ inline float attenuation<float>(double tau) { return rt::exp_mixed(-t
 // ---------------------------------------------------------------------------------------
 // Sample compaction.  A lane whose ray takes a step inside the plasma does not evaluate the
 // sample at once: it queues the point (ten doubles) in its wave's LDS area, up to K per lane.
-// When some lane's queue is full, or a ray with queued samples terminates, the wave evaluates
-// all queued samples together -- sample i of the flattened queue on lane i mod 64 -- so the
-// expensive part (MKS map, gather, fluid frame, closure) runs on full waves.  Each owner then
-// folds its own results into (I, tau) in the order the samples were taken, which keeps the
+// The wave evaluates queued samples together -- sample i of the selected list on lane i mod 64
+// -- so the expensive part (MKS map, gather, fluid frame, closure) runs on full waves: once 64
+// samples are queued (or a lane's queue is full) it evaluates the largest multiple of 64 of
+// them, oldest first across the lanes, and leaves the rest queued; when a ray with queued
+// samples terminates, or a full queue meets fewer than 64 samples, it evaluates everything.  Each owner folds its evaluated samples into (I, tau) in
+// the order they were taken and moves the rest to the front of its queue, which keeps the
 // backward transfer identical to evaluating every sample right after its step.
 // ---------------------------------------------------------------------------------------
 constexpr int N_FIELDS = 10;   // t, r, theta, phi, k^t, k^r, k^phi, |dlambda|, sin, cos
@@ -169,12 +173,15 @@ __device__ inline LaneInfo lane_info(const TraceParams& p, int job)
     return LaneInfo{J.a, J.grid, J.fast_snap, J.nu_base, J.n_nu};
 }
 
-template <int NNU, class TT>
+template <int NNU, class TT, bool MLPC = false>
 struct Queue {
-    // pending samples per lane: two while the LDS area stays within 32 KiB per wave
-    // (results are doubles in both precisions: an FP32 contribution carries its power-of-two
-    // scale, see Transfer<float>)
-    static constexpr int K = (64 * 2 * (N_FIELDS * 8 + 2 * NNU * 8 + 4) <= 32768) ? 2 : 1;
+    // pending samples per lane: the most (up to three) for which eight waves (two per SIMD)
+    // fit a compute unit's 160 KiB of LDS -- beside one copy of the network for the learned
+    // closure.  Results are doubles in both precisions (an FP32 contribution carries its
+    // power-of-two scale, see Transfer<float>).
+    static constexpr int bytes_for(int k) { return 64 * k * (N_FIELDS * 8 + 2 * NNU * 8 + 4) + 64 * 4; }
+    static constexpr int BUDGET = (163840 - (MLPC ? mlp::LDS_NET_BYTES : 0)) / 8;
+    static constexpr int K = bytes_for(3) <= BUDGET ? 3 : bytes_for(2) <= BUDGET ? 2 : 1;
     static constexpr int SLOTS = 64 * K;
     static constexpr size_t FIELD_BYTES = (size_t)N_FIELDS * SLOTS * sizeof(double);
     static constexpr size_t RES_BYTES = (size_t)2 * NNU * SLOTS * sizeof(double);
@@ -281,7 +288,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(64, (MLPC && WPE >= 2
                                amdgpu_waves_per_eu(WPE, 8)))
 trace_kernel(TraceParams p)
 {
-    using Q = Queue<NNU, TT>;
+    using Q = Queue<NNU, TT, MLPC>;
     constexpr int K = Q::K;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -434,25 +441,37 @@ trace_kernel(TraceParams p)
         c_pole += __popcll(__ballot(reflected));
 
         // ------------------------------------------------------------ evaluate queued samples
-        const bool must_flush = (pending == K) || (status != RAY_RUNNING && pending > 0);
-        if (__ballot(must_flush)) {
-            // flattened queue: lane L's samples follow those of the lanes below it
-            unsigned base_rank = 0, total = 0;
+        unsigned total = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) total += __popcll(__ballot(pending > k));
+        // a ray that ends with queued samples needs all of them now; a full queue needs one slot
+        const bool ending = __ballot(status != RAY_RUNNING && pending > 0) != 0ull;
+        const bool full = __ballot(pending == K) != 0ull;
+        if (ending || full || total >= 64) {
+            // whole rounds when there are 64 or more (the oldest samples, so a full queue always
+            // gets its first one evaluated), everything when a ray ends or fewer are queued
+            const unsigned n_eval = (ending || total < 64) ? total : (total & ~63u);
+            // select the oldest samples: queue layer k (each lane's k-th sample) before layer k + 1,
+            // within a layer by lane; `take` of this lane's samples are evaluated
+            int take = 0;
+            unsigned listed = 0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const unsigned long long b = __ballot(pending > k);
-                base_rank += lane_rank(b);
-                total += __popcll(b);
+                const unsigned rank = lane_rank(b);
+                if (pending > k && listed + rank < n_eval) {
+                    slot_map[listed + rank] = lane * K + k;
+                    take = k + 1;
+                }
+                const unsigned c = __popcll(b);
+                listed += (c < n_eval - listed) ? c : (n_eval - listed);
             }
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < pending) slot_map[base_rank + k] = lane * K + k;
             wave_lds_sync();
-            for (unsigned r0 = 0; r0 < total; r0 += 64) {
+            for (unsigned r0 = 0; r0 < n_eval; r0 += 64) {
                 const unsigned i = r0 + lane;
                 if (MLPC) {
                     // every lane takes part in the network evaluations of the round
-                    const bool has = i < total;
+                    const bool has = i < n_eval;
                     const int s = has ? slot_map[i] : 0;
                     double q[N_FIELDS];
 #pragma unroll
@@ -469,7 +488,7 @@ trace_kernel(TraceParams p)
                     }
                 } else {
                     bool zamo = false;
-                    if (i < total) {
+                    if (i < n_eval) {
                         const int s = slot_map[i];
                         double q[N_FIELDS];
 #pragma unroll
@@ -485,15 +504,15 @@ trace_kernel(TraceParams p)
                     c_zamo += __popcll(__ballot(zamo));
                 }
             }
-            c_samples += total;
+            c_samples += n_eval;
             wave_lds_sync();
-            // each owner folds its samples in order: I += exp(-tau) A, tau += dtau; with the
-            // optical-depth cut-off the ray ends after the first sample that makes it opaque at
-            // every frequency, and its later queued samples are dropped
+            // each owner folds its evaluated samples in order: I += exp(-tau) A, tau += dtau; with
+            // the optical-depth cut-off the ray ends after the first sample that makes it opaque
+            // at every frequency, and its later queued samples are dropped
             bool cut = false;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (k < pending && !cut) {
+                if (k < take && !cut) {
                     const int s = lane * K + k;
                     double tmin = 1e300;
 #pragma unroll
@@ -511,7 +530,27 @@ trace_kernel(TraceParams p)
                     }
                 }
             }
-            pending = 0;
+            // move the samples left queued to the front of this lane's queue
+            const int left = cut ? 0 : pending - take;
+            if (K > 1 && take > 0) {
+#pragma unroll
+                for (int j = 0; j + 1 < K; ++j) {
+                    if (j < left) {
+#pragma unroll
+                        for (int f = 0; f < N_FIELDS; ++f)
+                            fields[f * Q::SLOTS + lane * K + j] = fields[f * Q::SLOTS + lane * K + j + take];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j + 1 < K; ++j) {
+                    int v = qstep[j];
+#pragma unroll
+                    for (int m = 1; m < K; ++m)
+                        if (m == take && j + m < K) v = qstep[j + m];
+                    qstep[j] = v;
+                }
+            }
+            pending = left;
             wave_lds_sync();
         }
 
@@ -656,13 +695,17 @@ hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const 
 size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc)
 {
     const int waves = threads / 64;
-    auto per = [&](auto tt) -> size_t {
+    auto per_q = [&](auto tt, auto m) -> size_t {
         using TT = decltype(tt);
-        if (max_nu <= 1) return Queue<1, TT>::PER_WAVE;
-        if (max_nu <= 4) return Queue<4, TT>::PER_WAVE;
-        if (max_nu <= 8) return Queue<8, TT>::PER_WAVE;
-        if (max_nu <= 16) return Queue<16, TT>::PER_WAVE;
-        return Queue<32, TT>::PER_WAVE;
+        constexpr bool M = decltype(m)::value;
+        if (max_nu <= 1) return Queue<1, TT, M>::PER_WAVE;
+        if (max_nu <= 4) return Queue<4, TT, M>::PER_WAVE;
+        if (max_nu <= 8) return Queue<8, TT, M>::PER_WAVE;
+        if (max_nu <= 16) return Queue<16, TT, M>::PER_WAVE;
+        return Queue<32, TT, M>::PER_WAVE;
+    };
+    auto per = [&](auto tt) -> size_t {
+        return mlpc ? per_q(tt, std::true_type{}) : per_q(tt, std::false_type{});
     };
     return waves * (fp32 ? per(0.0f) : per(0.0)) + (mlpc ? (size_t)mlp::LDS_NET_BYTES : 0);
 }
