@@ -129,7 +129,7 @@ __device__ inline bool in_plasma(const DevGrid& g, double r) { return r >= g.r_i
 __device__ inline void sample_fluid(const DevGrid& g, int slow_light, int fast_snap, const double* y, double out[4])
 {
     const double r = y[1];
-    const double x1 = ::log(r);
+    const double x1 = rt::log_pos(r);
     const double x2 = mks_x2(g.hslope, y[2], x2_start(g, y[2]));
     double f1 = (x1 - g.lnr_in) * g.inv_d1 - 0.5;
     double f2 = x2 * g.n2 - 0.5;

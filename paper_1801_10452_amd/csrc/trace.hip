@@ -55,7 +55,7 @@ struct Transfer<double> {
         emits = (ne > 0.0 && the > 0.0 && bf > 0.0 && sinb > 0.0);
         k2_inv = 0.0;
         if (emits && p.closure != CL_CONST)
-            k2_inv = (p.closure == CL_K2_PAPER) ? 1.0 / (2.0 * the * the) : ::exp(-pl::ln_k2(p.k2, ::log(the)));
+            k2_inv = (p.closure == CL_K2_PAPER) ? 1.0 / (2.0 * the * the) : ::exp(-pl::ln_k2(p.k2, rt::log_pos(the)));
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
@@ -102,7 +102,7 @@ struct Transfer<float> {
         k2_inv = 0.0f;
         if (emits && p.closure != CL_CONST)
             k2_inv = (p.closure == CL_K2_PAPER) ? 1.0f / (2.0f * the * the)
-                                               : rt::exp_mixed(-pl::ln_k2(p.k2, ::log(fl[1])));
+                                               : rt::exp_mixed(-pl::ln_k2(p.k2, rt::log_pos(fl[1])));
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
@@ -242,14 +242,14 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
     }
     c_zamo += __popcll(__ballot(zamo));
     const double nuc = pl::NUC_PER_GAUSS * fl[2];
-    const float lth = (float)::log(fl[1] > 0.0 ? fl[1] : 1.0);
+    const float lth = (float)rt::log_pos(fl[1] > 0.0 ? fl[1] : 1.0);
     const double ds = nr * q[7] * p.length_unit;
     const double inr3 = has ? rt::rcp_nr(nr * nr * nr) : 0.0;
 #pragma unroll 1
     for (int f = 0; f < NNU; ++f) {
         const bool act = has && f < li.n_nu;
         const double nu = act ? p.nu[li.nu_base + f] * nr : nuc;
-        const float lx = (float)::log(nu / nuc);
+        const float lx = (float)rt::log_pos(nu / nuc);
         const bool inb = act && tr.emits && mlp::in_box(lx, lth, (float)cb);
         c_fallback += __popcll(__ballot(act && tr.emits && !inb));
         const float x0 = inb ? mlp::norm_lx(lx) : 0.0f, x1 = inb ? mlp::norm_lt(lth) : 0.0f,
@@ -393,6 +393,7 @@ trace_kernel(TraceParams p)
         if (active) {
             const rk::Spin<double> sp = rk::make_spin(a, M);
             const double dl = -rk::step_size(p.eps, y);
+            const double th0 = y[2], s0 = sth, c0 = cth;
             if (INTEG == INTEG_RK2) {
                 rk::rk2_step(sp, y, dl, sth, cth);
             } else if (INTEG == INTEG_VERLET) {
@@ -411,7 +412,12 @@ trace_kernel(TraceParams p)
             } else {
                 reflected = rk::reflect_pole(y);
                 if (reflected) have_acc = false;   // the carried derivative belongs to the old chart
-                rt::sincos_small(y[2], &sth, &cth);
+                // sin and cos of the new theta from those of the old one (the step moves theta
+                // little); after a reflection from scratch
+                if (reflected)
+                    rt::sincos_small(y[2], &sth, &cth);
+                else
+                    rk::sincos_shift(th0, s0, c0, y[2], &sth, &cth);
                 if (y[1] < r_stop)
                     status = RAY_HORIZON;
                 else if (y[1] > r_esc)
