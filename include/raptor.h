@@ -192,13 +192,16 @@ typedef struct {
     int32_t refill_threshold;    /* a wave refills its idle lanes once this many are idle (1..64) */
     int32_t tile_width;          /* pixels per tile row: 8, 16, 32 or 64 (a tile is 64 rays) */
     int32_t min_waves_per_simd;  /* 1, 2 or 3: the kernel variant compiled for at least that many
-                                    waves per SIMD (register cap 512, 256 or 168) */
+                                    waves per SIMD (register cap 512, 256 or 168); the 3-wave
+                                    variant sizes its LDS sample queue for 12 waves per CU */
     int32_t reserved[3];
 } raptor_plan;
 
 /* Current plan for (n_nu, transfer_prec, closure) (the default plan if none was set or tuned:
- * 256 threads, as many work-groups as fit, refill at 1 idle lane, 8-pixel tile rows, the
- * 2-waves-per-SIMD variant; 512 threads for the learned closures). */
+ * 256 threads, as many work-groups as fit, refill at 1 idle lane, 8-pixel tile rows, and the
+ * variant with the most waves per SIMD (3, 2, then 1) whose RK4 kernel keeps its registers
+ * without spilling to scratch; for the learned closures 512 threads and the 2-waves-per-SIMD
+ * variant).  RK2 and Verlet runs use the 2-waves-per-SIMD kernel under any plan. */
 raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
                               raptor_plan* out);
 /* Install a plan for (n_nu, transfer_prec, closure); RAPTOR_E_INVALID if a field is out of range,

@@ -22,9 +22,16 @@ FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I" + os.path.
          "-Wno-unused-command-line-argument"]
 
 
+# The geodesic kernels keep their polynomial and step constants as scalar-register literals next
+# to each use: hoisting them out of the ray loop (machine LICM) overflows the scalar register
+# file and spills them into vector-register lanes, which costs more vector instructions than it
+# saves.
+PER_SOURCE = {"trace.hip": ["-mllvm", "-disable-machine-licm"], "disk.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+    cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + PER_SOURCE.get(src, [])
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -163,15 +163,15 @@ raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* p
               "reading kernel attributes");
     while (pl->p.threads > 64 && pl->p.threads > max_threads) pl->p.threads /= 2;
     // the per-wave sample queue lives in LDS: shrink the work-group until it fits
-    while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc) > ctx->lds_per_block)
+    while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4) > ctx->lds_per_block)
         pl->p.threads /= 2;
-    if (trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc) > ctx->lds_per_block)
+    if (trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4) > ctx->lds_per_block)
         return fail(ctx, RAPTOR_E_UNSUPPORTED, "the sample queue of one wave exceeds the LDS of a work-group");
     int per_cu = pl->p.blocks_per_cu;
     if (per_cu == 0) {
         RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                       &per_cu, trace_kernel_symbol(max_nu, fp32, pl->p.min_waves_per_simd, mlpc), pl->p.threads,
-                      trace_kernel_lds(max_nu, fp32, pl->p.threads, mlpc)),
+                      trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4)),
                   "querying occupancy");
         per_cu = std::max(per_cu, 1);
     }
@@ -188,7 +188,18 @@ raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, 
         return RAPTOR_OK;
     }
     LaunchPlan pl;
-    if (mlpc) pl.p.threads = 512;   // eight waves share one LDS copy of the network
+    if (mlpc) {
+        pl.p.threads = 512;   // eight waves share one LDS copy of the network
+    } else {
+        // the most waves per SIMD whose instantiation holds its registers without scratch
+        for (int w = 3; w >= 1; --w) {
+            int regs = 0, spill = 0, maxt = 0;
+            RAPTOR_CK(trace_kernel_attributes(max_nu, fp32, w, false, INTEG_RK4, &regs, &spill, &maxt),
+                      "reading kernel attributes");
+            pl.p.min_waves_per_simd = w;
+            if (spill == 0) break;
+        }
+    }
     raptor_status s = resolve_plan(ctx, max_nu, fp32, &pl, mlpc);
     if (s != RAPTOR_OK) return s;
     ctx->plans[key] = pl;
@@ -825,7 +836,7 @@ raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer
               "reading kernel attributes");
     RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                   &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd, mlpc), plan->threads,
-                  trace_kernel_lds(n_nu, fp32, plan->threads, mlpc)),
+                  trace_kernel_lds(n_nu, fp32, plan->min_waves_per_simd, plan->threads, mlpc, INTEG_RK4)),
               "querying occupancy");
     if (vgprs) *vgprs = regs;
     if (scratch_bytes) *scratch_bytes = spill;

@@ -124,24 +124,33 @@ __host__ __device__ inline void ks_rhs(const Spin<T>& sp, const T* y, T* f)
 }
 
 // sin and cos of theta + d from s0 = sin(theta), c0 = cos(theta): Taylor polynomials of sin d
-// (through d^13) and cos d (through d^14), whose truncation error is below 1e-21 for
-// |d| <= 0.25, and the angle-addition formulas; larger |d| falls back to a full sincos.
+// (through d^9) and cos d (through d^10), whose truncation errors for |d| <= 0.1 are below
+// 3e-18 relative and 3e-21 absolute, and the angle-addition formulas; larger |d| falls back to
+// a full sincos.  With the step rule's eps = 0.05 a stage moves theta by at most about 0.08.
+// The polynomials are summed as power sums, each coefficient a multiplicand: a coefficient that
+// is an FMA addend must be copied into vector registers first, one multiplicand is read from
+// scalar registers as it is.
 template <class T>
 __host__ __device__ inline void sincos_shift(T th0, T s0, T c0, T th, T* s, T* c)
 {
     using namespace rt;
     const T d = th - th0;
-    if (fabs_(d) > T(0.25)) {
+    if (fabs_(d) > T(0.1)) {
         sincos_small(th, s, c);
         return;
     }
-    const T d2 = d * d;
-    const T ps = T(-1.0 / 6.0) + d2 * (T(1.0 / 120.0) + d2 * (T(-1.0 / 5040.0) + d2 * (T(1.0 / 362880.0)
-               + d2 * (T(-1.0 / 39916800.0) + d2 * T(1.0 / 6227020800.0)))));
-    const T sd = d + d * d2 * ps;
-    const T pc = T(1.0 / 24.0) + d2 * (T(-1.0 / 720.0) + d2 * (T(1.0 / 40320.0) + d2 * (T(-1.0 / 3628800.0)
-               + d2 * (T(1.0 / 479001600.0) + d2 * T(-1.0 / 87178291200.0)))));
-    const T cdm1 = d2 * (T(-0.5) + d2 * pc);   // cos d - 1
+    // smallest terms first
+    const T d2 = d * d, d4 = d2 * d2, d6 = d4 * d2, d8 = d4 * d4;
+    T ps = T(1.0 / 362880.0) * d8;
+    ps = ps + T(-1.0 / 5040.0) * d6;
+    ps = ps + T(1.0 / 120.0) * d4;
+    ps = ps + T(-1.0 / 6.0) * d2;            // sin d / d - 1
+    const T sd = d + d * ps;
+    T cdm1 = T(-1.0 / 3628800.0) * (d8 * d2);
+    cdm1 = cdm1 + T(1.0 / 40320.0) * d8;
+    cdm1 = cdm1 + T(-1.0 / 720.0) * d6;
+    cdm1 = cdm1 + T(1.0 / 24.0) * d4;
+    cdm1 = cdm1 + T(-0.5) * d2;              // cos d - 1
     *s = s0 + (s0 * cdm1 + c0 * sd);
     *c = c0 + (c0 * cdm1 - s0 * sd);
 }

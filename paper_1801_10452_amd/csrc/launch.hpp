@@ -18,7 +18,11 @@ hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, in
 // the 2-waves-per-SIMD variant only)
 const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = false, int integ = INTEG_RK4);
 // dynamic LDS bytes of a trace-kernel work-group of `threads` lanes (mlpc: plus the staged network)
-size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc);
+// Dynamic LDS bytes of a trace launch; the same (wpe, mlpc, integ) select the instantiation in
+// trace_kernel_symbol, whose sample queue this sizes.
+size_t trace_kernel_lds(int max_nu, bool fp32, int wpe, int threads, bool mlpc, int integ);
+// Waves-per-SIMD variant actually instantiated for a requested one.
+int kernel_wpe(int wpe, bool mlpc, int integ);
 
 // ---- thin disk (disk.hip)
 hipError_t launch_disk(const DiskParams& p, int blocks, hipStream_t st);

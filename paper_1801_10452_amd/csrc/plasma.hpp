@@ -89,7 +89,7 @@ __device__ inline void bilinear(const DevGrid& g, int s, int i0, int j0, double 
 __device__ inline double modulation(const DevGrid& g, double r, double ph, double ts)
 {
     if (g.mod_amp == 0.0) return 1.0;
-    const double om = 1.0 / (r * ::sqrt(r) + g.a_gen);
+    const double om = rt::rcp_nr(r * r * rt::rsqrt_nr(r) + g.a_gen);   // 1 / (r^1.5 + a_gen)
     // reduce the phase by whole turns (two-term 2 pi, exact head) before the small-argument sincos
     const double arg = ph - om * ts;
     const double turns = __builtin_rint(arg * 0.15915494309189535);

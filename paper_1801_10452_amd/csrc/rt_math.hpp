@@ -51,12 +51,28 @@ __host__ __device__ inline void sincos_small(double x, double* s, double* c)
     double r = __builtin_fma(-k, 1.5707963267941523, x);
     r = __builtin_fma(-k, 7.443547480486623e-13, r);
     r = __builtin_fma(-k, -1.2536990206932499e-29, r);
-    const double r2 = r * r;
-    const double ps = -1.0 / 6.0 + r2 * (1.0 / 120.0 + r2 * (-1.0 / 5040.0 + r2 * (1.0 / 362880.0 + r2 * (-1.0 / 39916800.0
-                    + r2 * (1.0 / 6227020800.0 + r2 * (-1.0 / 1307674368000.0 + r2 * (1.0 / 355687428096000.0)))))));
-    const double pc = -0.5 + r2 * (1.0 / 24.0 + r2 * (-1.0 / 720.0 + r2 * (1.0 / 40320.0 + r2 * (-1.0 / 3628800.0
-                    + r2 * (1.0 / 479001600.0 + r2 * (-1.0 / 87178291200.0 + r2 * (1.0 / 20922789888000.0
-                    + r2 * (-1.0 / 6402373705728000.0))))))));
+    // power sums in y = r^2, smallest terms first (each coefficient a multiplicand, so that it is
+    // read from scalar registers instead of being copied into vector registers as an FMA addend)
+    const double y = r * r, y2 = y * y, y3 = y2 * y, y4 = y2 * y2;
+    const double y5 = y4 * y, y6 = y4 * y2, y7 = y4 * y3, y8 = y4 * y4;
+    double ps = (1.0 / 355687428096000.0) * y7;
+    ps = ps + (-1.0 / 1307674368000.0) * y6;
+    ps = ps + (1.0 / 6227020800.0) * y5;
+    ps = ps + (-1.0 / 39916800.0) * y4;
+    ps = ps + (1.0 / 362880.0) * y3;
+    ps = ps + (-1.0 / 5040.0) * y2;
+    ps = ps + (1.0 / 120.0) * y;
+    ps = ps + (-1.0 / 6.0);
+    double pc = (-1.0 / 6402373705728000.0) * y8;
+    pc = pc + (1.0 / 20922789888000.0) * y7;
+    pc = pc + (-1.0 / 87178291200.0) * y6;
+    pc = pc + (1.0 / 479001600.0) * y5;
+    pc = pc + (-1.0 / 3628800.0) * y4;
+    pc = pc + (1.0 / 40320.0) * y3;
+    pc = pc + (-1.0 / 720.0) * y2;
+    pc = pc + (1.0 / 24.0) * y;
+    pc = pc + (-0.5);
+    const double r2 = y;
     const double sn = r + r * r2 * ps;
     const double cs = 1.0 + r2 * pc;
     const int q = (int)k & 3;
@@ -79,6 +95,17 @@ __host__ __device__ inline double rcp_nr(double x)
     return __builtin_fma(r, e, r);
 #else
     return 1.0 / x;
+#endif
+}
+
+// Float reciprocal: the hardware estimate (about 1 ulp) refined by one Newton-Raphson step.
+__host__ __device__ inline float rcpf_nr(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+#else
+    return 1.0f / x;
 #endif
 }
 
@@ -127,21 +154,36 @@ __host__ __device__ inline double log_pos(double x)
     }
     const double s = (m - 1.0) * rcp_nr(m + 1.0);
     const double s2 = s * s;
-    const double p = 1.0 / 3.0 + s2 * (1.0 / 5.0 + s2 * (1.0 / 7.0 + s2 * (1.0 / 9.0 + s2 * (1.0 / 11.0
-                   + s2 * (1.0 / 13.0 + s2 * (1.0 / 15.0 + s2 * (1.0 / 17.0)))))));
+    const double s4 = s2 * s2, s6 = s4 * s2, s8 = s4 * s4, s10 = s8 * s2, s12 = s8 * s4, s14 = s8 * s6;
+    double p = (1.0 / 17.0) * s14;
+    p = p + (1.0 / 15.0) * s12;
+    p = p + (1.0 / 13.0) * s10;
+    p = p + (1.0 / 11.0) * s8;
+    p = p + (1.0 / 9.0) * s6;
+    p = p + (1.0 / 7.0) * s4;
+    p = p + (1.0 / 5.0) * s2;
+    p = p + 1.0 / 3.0;
     const double lm = 2.0 * s + 2.0 * s * s2 * p;
     const double de = (double)e;
     return de * 0.6931471805599453094 + (de * 2.319046813846299558e-17 + lm);
 }
 
-// Cube root of a positive double below ~1e38: the float cube root refined by one Newton step
-// in double (t <- t + (x - t^3) / (3 t^2), the quotient's float precision only scaling the
-// already small correction), relative error near 1e-14.
+// Cube root of a positive double in the float range: 2^(log2(x)/3) from the hardware float
+// log2 and exp2 (relative error a few 1e-6 for |log2 x| up to ~128), refined by one Newton step
+// in double, t <- t + (x - t^3) / (3 t^2), which squares the error (the quotient's float
+// precision only scales the already small correction): relative error near 1e-11.
 __host__ __device__ inline double cbrt_refined(double x)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float xf = (float)x;
+    const float tf = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (1.0f / 3.0f));
+    const double td = (double)tf;
+    return td + (x - td * td * td) * (double)__builtin_amdgcn_rcpf(3.0f * tf * tf);
+#else
     const float tf = ::cbrtf((float)x);
     const double td = (double)tf;
     return td + (x - td * td * td) * (double)(1.0f / (3.0f * tf * tf));
+#endif
 }
 
 // ---------------------------------------------------------------- operation counting (host only)

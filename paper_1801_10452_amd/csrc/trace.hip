@@ -82,7 +82,7 @@ struct Transfer<double> {
 // flushing to zero.  The results (contribution and optical depth of the step) are doubles.
 template <>
 struct Transfer<float> {
-    float ne, the, nu_s, k2_inv, ds, inr3;
+    float ne, the, inv_the, nu_s, k2_inv, ds, inr3;
     double nr_inv_nus;   // nu_r / nu_s: X = nu_obs nu_r / nu_s in double
     double nr;
     bool emits;
@@ -90,6 +90,7 @@ struct Transfer<float> {
     {
         ne = (float)fl[0];
         the = (float)fl[1];
+        inv_the = rt::rcpf_nr(the);
         nr = nr_;
         ds = (float)dsv;
         inr3 = (float)rt::rcp_nr(nr_ * nr_ * nr_);
@@ -128,8 +129,10 @@ struct Transfer<float> {
         const float jm = 1.1396857174835936e-29f * ne * nu_s * k2_inv * t * tc * tc * em;   // j = jm 2^-n
         const float nuf = (float)(nu_obs * nr);
         const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
-        const float S = q * q * q / ::expm1f((float)pl::H_OVER_MEC2 * nuf / the);
-        const float dtm = jm / S * ds;                            // dtau = dtm 2^-n
+        const float q3 = q * q * q;                               // 2 h nu^3 / c^2
+        const float em1 = ::expm1f((float)pl::H_OVER_MEC2 * nuf * inv_the);
+        const float S = q3 * rt::rcpf_nr(em1);                    // B_nu
+        const float dtm = jm * em1 * rt::rcpf_nr(q3) * ds;        // dtau = dtm 2^-n
         dtau = (double)dtm * scale;
         if (dtau > 1e-8) {
             A = (double)(S * -::expm1f(-(float)dtau) * inr3);
@@ -173,14 +176,16 @@ __device__ inline LaneInfo lane_info(const TraceParams& p, int job)
     return LaneInfo{J.a, J.grid, J.fast_snap, J.nu_base, J.n_nu};
 }
 
-template <int NNU, class TT, bool MLPC = false>
+template <int NNU, class TT, bool MLPC, int WPE>
 struct Queue {
-    // pending samples per lane: the most (up to three) for which eight waves (two per SIMD)
-    // fit a compute unit's 160 KiB of LDS -- beside one copy of the network for the learned
-    // closure.  Results are doubles in both precisions (an FP32 contribution carries its
-    // power-of-two scale, see Transfer<float>).
+    // pending samples per lane: the most (up to three) for which the waves of the variant's
+    // occupancy (two per SIMD, or three for the 3-waves-per-SIMD variant) fit a compute unit's
+    // 160 KiB of LDS -- beside one copy of the network for the learned closure.  Results are
+    // doubles in both precisions (an FP32 contribution carries its power-of-two scale, see
+    // Transfer<float>).
     static constexpr int bytes_for(int k) { return 64 * k * (N_FIELDS * 8 + 2 * NNU * 8 + 4) + 64 * 4; }
-    static constexpr int BUDGET = (163840 - (MLPC ? mlp::LDS_NET_BYTES : 0)) / 8;
+    static constexpr int WAVES_PER_CU = 4 * (WPE >= 3 ? 3 : 2);
+    static constexpr int BUDGET = (163840 - (MLPC ? mlp::LDS_NET_BYTES : 0)) / WAVES_PER_CU;
     static constexpr int K = bytes_for(3) <= BUDGET ? 3 : bytes_for(2) <= BUDGET ? 2 : 1;
     static constexpr int SLOTS = 64 * K;
     static constexpr size_t FIELD_BYTES = (size_t)N_FIELDS * SLOTS * sizeof(double);
@@ -288,7 +293,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(64, (MLPC && WPE >= 2
                                amdgpu_waves_per_eu(WPE, 8)))
 trace_kernel(TraceParams p)
 {
-    using Q = Queue<NNU, TT, MLPC>;
+    using Q = Queue<NNU, TT, MLPC, WPE>;
     constexpr int K = Q::K;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -643,18 +648,30 @@ __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* sta
 
 // Instantiations: RK4 with every register budget (1, 2 or 3 waves per SIMD) and the learned
 // closure (1 or 2); the second-order integrators with the 2-waves-per-SIMD budget only.
+}  // namespace
+
+int kernel_wpe(int wpe, bool mlpc, int integ)
+{
+    if (integ != INTEG_RK4) return 2;   // RK2 and Verlet are instantiated for two waves per SIMD only
+    if (mlpc) return wpe >= 2 ? 2 : 1;
+    return wpe >= 3 ? 3 : wpe == 2 ? 2 : 1;
+}
+
+namespace {
+
 template <int NNU, class TT>
 const void* symbol_of(int wpe, bool mlpc, int integ)
 {
+    const int w = kernel_wpe(wpe, mlpc, integ);
     if (integ == INTEG_RK2) return (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK2>;
     if (integ == INTEG_VERLET || integ == INTEG_VERLET_CORR)
         return (const void*)trace_kernel<NNU, TT, 2, false, INTEG_VERLET>;
     if (mlpc)
-        return wpe >= 2 ? (const void*)trace_kernel<NNU, TT, 2, true, INTEG_RK4>
-                        : (const void*)trace_kernel<NNU, TT, 1, true, INTEG_RK4>;
-    return wpe >= 3 ? (const void*)trace_kernel<NNU, TT, 3, false, INTEG_RK4>
-         : wpe == 2 ? (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK4>
-                    : (const void*)trace_kernel<NNU, TT, 1, false, INTEG_RK4>;
+        return w == 2 ? (const void*)trace_kernel<NNU, TT, 2, true, INTEG_RK4>
+                      : (const void*)trace_kernel<NNU, TT, 1, true, INTEG_RK4>;
+    return w == 3 ? (const void*)trace_kernel<NNU, TT, 3, false, INTEG_RK4>
+         : w == 2 ? (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK4>
+                  : (const void*)trace_kernel<NNU, TT, 1, false, INTEG_RK4>;
 }
 
 template <class TT>
@@ -680,7 +697,7 @@ hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, in
     const void* fn = trace_kernel_symbol(max_nu, fp32, wpe, p.closure >= CL_MLP, p.integrator);
     void* args[] = {const_cast<TraceParams*>(&p)};
     return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args,
-                           trace_kernel_lds(max_nu, fp32, threads, p.closure >= CL_MLP), st);
+                           trace_kernel_lds(max_nu, fp32, wpe, threads, p.closure >= CL_MLP, p.integrator), st);
 }
 
 size_t flux_partials(int n_jobs, int max_nu) { return (size_t)n_jobs * max_nu * FLUX_SPLIT; }
@@ -698,17 +715,23 @@ hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const 
     return hipGetLastError();
 }
 
-size_t trace_kernel_lds(int max_nu, bool fp32, int threads, bool mlpc)
+size_t trace_kernel_lds(int max_nu, bool fp32, int wpe, int threads, bool mlpc, int integ)
 {
+    // the queue of the instantiation that trace_kernel_symbol picks for the same arguments
+    const int w = kernel_wpe(wpe, mlpc, integ);
     const int waves = threads / 64;
-    auto per_q = [&](auto tt, auto m) -> size_t {
+    auto per_w = [&](auto tt, auto m, auto w) -> size_t {
         using TT = decltype(tt);
         constexpr bool M = decltype(m)::value;
-        if (max_nu <= 1) return Queue<1, TT, M>::PER_WAVE;
-        if (max_nu <= 4) return Queue<4, TT, M>::PER_WAVE;
-        if (max_nu <= 8) return Queue<8, TT, M>::PER_WAVE;
-        if (max_nu <= 16) return Queue<16, TT, M>::PER_WAVE;
-        return Queue<32, TT, M>::PER_WAVE;
+        constexpr int W = decltype(w)::value;
+        if (max_nu <= 1) return Queue<1, TT, M, W>::PER_WAVE;
+        if (max_nu <= 4) return Queue<4, TT, M, W>::PER_WAVE;
+        if (max_nu <= 8) return Queue<8, TT, M, W>::PER_WAVE;
+        if (max_nu <= 16) return Queue<16, TT, M, W>::PER_WAVE;
+        return Queue<32, TT, M, W>::PER_WAVE;
+    };
+    auto per_q = [&](auto tt, auto m) -> size_t {
+        return w == 3 ? per_w(tt, m, std::integral_constant<int, 3>{}) : per_w(tt, m, std::integral_constant<int, 2>{});
     };
     auto per = [&](auto tt) -> size_t {
         return mlpc ? per_q(tt, std::true_type{}) : per_q(tt, std::false_type{});
