@@ -9,9 +9,11 @@
 // on (r, theta) only,
 //     Gamma^a_{mn} k^m k^n = g^{ab} ( Gdot_{bn} k^n - 1/2 (d_b g_{mn}) k^m k^n ),
 //     Gdot_{bn} = k^r d_r g_{bn} + k^theta d_theta g_{bn},
-// which is the connection formula of Sec. 2.1 contracted with k twice; only the seven
-// non-zero KS metric components and their r and theta derivatives appear, and the inverse
-// metric is used in its closed form.
+// which is the connection formula of Sec. 2.1 contracted with k twice.  The Kerr-Schild form
+// of the metric (Sec. 2.1) is used to contract it: g = g0 + z l l with z = 2 M r / Sigma, the
+// null covector l = (1, 1, 0, -a sin^2) and g0 flat space in oblate spheroidal coordinates, so
+// that F_b splits into a short flat-space part and a z l l part built from z, its two
+// derivatives and l.k; the inverse metric is used in its closed form.
 #pragma once
 #include "rt_math.hpp"
 
@@ -21,6 +23,7 @@ namespace rk {
 template <class T>
 struct Spin {
     T a, a2, M;
+    T twoM, m2a, twoa2;   // 2 M, -2 a, 2 a^2
 };
 
 template <class T>
@@ -30,81 +33,56 @@ __host__ __device__ inline Spin<T> make_spin(T a, T M)
     s.a = a;
     s.a2 = a * a;
     s.M = M;
+    s.twoM = T(2.0) * M;
+    s.m2a = T(-2.0) * a;
+    s.twoa2 = T(2.0) * s.a2;
     return s;
 }
 
 // dk/dlambda = -Gamma k k at state y, given s = sin(theta), c = cos(theta).
-// F_b = Gdot_{bn} k^n - 1/2 (d_b g_mn) k^m k^n is accumulated one metric component at a time
-// (each component's r and theta derivatives enter F and are then dead), then raised with the
-// closed-form inverse metric.
+// F_b = Gdot_{bn} k^n - 1/2 (d_b g_mn) k^m k^n for g = g0 + z l l:
+//   z l l part:  zd l_b L + z (k.d l_b) L + z l_b Ld - 1/2 (d_b z) L^2 - z L (d_b l_m) k^m,
+//   with L = l.k, zd = k^r dz/dr + k^theta dz/dtheta, and d_theta l_phi = -2 a s c the only
+//   derivative of l (Ld = k^theta (d_theta l_phi) k^phi);
+//   flat part:   g0 = diag(-1, 1, Sigma) with g0_{r phi} = l_phi, g0_{phi phi} = (r^2 + a^2) sin^2;
+// then raised with the closed-form inverse metric.
 template <class T>
 __host__ __device__ inline void ks_accel(const Spin<T>& sp, const T* y, T s, T c, T* dk)
 {
     using namespace rt;
-    const T a = sp.a, a2 = sp.a2, M = sp.M;
+    const T a = sp.a, a2 = sp.a2;
     const T r = y[1];
     const T kt = y[4], kr = y[5], kh = y[6], kp = y[7];
-    const T s2 = s * s, c2 = c * c, sc2 = T(2.0) * s * c;
+    const T s2 = s * s, sc = s * c;
     const T r2 = r * r;
-    const T sig = r2 + a2 * c2;
-    const T w = rcp_nr(sig * s2);         // 1/(Sigma sin^2)
-    const T isig = w * s2;                // 1/Sigma
-    const T twoMr = T(2.0) * M * r;
-    const T z = twoMr * isig;             // 2 M r / Sigma
-    const T z1 = T(1.0) + z;
-    const T zr = T(2.0) * M * (a2 * c2 - r2) * (isig * isig);   // dz/dr
-    const T zt = z * a2 * sc2 * isig;                           // dz/dtheta
-    const T ktr = kt + kr;
+    const T a2c2 = a2 * (c * c);
+    const T sig = r2 + a2c2;
+    const T w = rcp_nr(sig * s2);                           // 1/(Sigma sin^2)
+    const T isig = w * s2;                                  // 1/Sigma
+    const T twoMr = sp.twoM * r;
+    const T z = twoMr * isig;                               // 2 M r / Sigma
+    const T zr = sp.twoM * (a2c2 - r2) * (isig * isig);     // dz/dr
+    const T zt = z * (sp.twoa2 * sc) * isig;                // dz/dtheta
+    const T lp = -a * s2;                                   // l_phi
+    const T dl = sp.m2a * sc;                               // d l_phi / dtheta
+    const T L = (kt + kr) + lp * kp;                        // l.k
+    const T ld = kh * dl;                                   // k^c d_c l_phi
+    const T Ld = ld * kp;
+    const T zd = kr * zr + kh * zt;                         // k^c d_c z
+    const T L2 = L * L;
+    const T zL = z * L;
     const T khh = kh * kh, kpp = kp * kp;
-    // g_tt, g_tr, g_rr: d g = dz; their k k contraction is (k^t + k^r)^2
-    const T gd_z = kr * zr + kh * zt;
-    const T hq_z = T(0.5) * ktr * ktr;
-    T F_t = gd_z * ktr;
-    T F_r = gd_z * ktr - zr * hq_z;
-    T F_h = -zt * hq_z;
-    // g_tp = -a z sin^2: d_r = -a sin^2 dz/dr, d_theta = -a (2 s c z + sin^2 dz/dtheta)
-    const T dr_tp = -a * s2 * zr;
-    {
-        const T dt_tp = -a * (sc2 * z + s2 * zt);
-        const T gd = kr * dr_tp + kh * dt_tp;
-        F_t = F_t + gd * kp;
-        T F_p0 = gd * kt;
-        F_r = F_r - dr_tp * kt * kp;
-        F_h = F_h - dt_tp * kt * kp;
-        dk[3] = F_p0;   // F_p accumulates in dk[3]
-    }
-    // g_rp = -a sin^2 (1 + z): d_r = d_r g_tp, d_theta = -a (2 s c (1 + z) + sin^2 dz/dtheta)
-    {
-        const T dt_rp = -a * (sc2 * z1 + s2 * zt);
-        const T gd = kr * dr_tp + kh * dt_rp;
-        F_r = F_r + gd * kp - dr_tp * kr * kp;
-        dk[3] = dk[3] + gd * kr;
-        F_h = F_h - dt_rp * kr * kp;
-    }
-    // g_hh = Sigma: d_r = 2 r, d_theta = -2 a^2 s c
-    {
-        const T dr_hh = T(2.0) * r;
-        const T dt_hh = -a2 * sc2;
-        const T gd = kr * dr_hh + kh * dt_hh;
-        F_h = F_h + gd * kh - T(0.5) * dt_hh * khh;
-        F_r = F_r - T(0.5) * dr_hh * khh;
-    }
-    // g_pp = sin^2 (Sigma + a^2 sin^2 (1 + z))
-    {
-        const T s4 = s2 * s2;
-        const T dr_pp = T(2.0) * r * s2 + a2 * s4 * zr;
-        const T dt_pp = sc2 * (sig - a2 * s2) + T(2.0) * a2 * s2 * sc2 * z1 + a2 * s4 * zt;
-        const T gd = kr * dr_pp + kh * dt_pp;
-        dk[3] = dk[3] + gd * kp;
-        F_r = F_r - T(0.5) * dr_pp * kpp;
-        F_h = F_h - T(0.5) * dt_pp * kpp;
-    }
-    const T F_p = dk[3];
+    const T ra = r2 + a2;
+    const T F1t = zd * L + z * Ld;                          // z l l part of F_t (the flat part is 0)
+    const T F_t = F1t;
+    const T F_r = F1t - T(0.5) * zr * L2 + (Ld - r * (khh + s2 * kpp));
+    const T F_h = T(2.0) * r * kr * kh - T(0.5) * zt * L2 - dl * kp * (zL + kr) - sc * (a2 * khh + ra * kpp);
+    const T F_p = lp * F1t + zL * ld + kr * (T(2.0) * r * s2 * kp + ld) + T(2.0) * ra * sc * kh * kp;
     // inverse metric: g^tt = -(1+z), g^tr = z, g^rr = Delta/Sigma, g^rp = a/Sigma,
     // g^hh = 1/Sigma, g^pp = 1/(Sigma sin^2)
-    const T gi_rr = (r2 - twoMr + a2) * isig;
+    const T gi_rr = (ra - twoMr) * isig;
     const T ai = a * isig;
-    dk[0] = z1 * F_t - z * F_r;
+    dk[0] = F_t + z * (F_t - F_r);
     dk[1] = -(z * F_t + gi_rr * F_r + ai * F_p);
     dk[2] = -isig * F_h;
     dk[3] = -(ai * F_r + w * F_p);
