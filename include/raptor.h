@@ -75,19 +75,33 @@ void raptor_destroy(raptor_ctx* ctx);
  * With ctx == NULL, the message of the last failed raptor_create on this thread. */
 const char* raptor_last_error(const raptor_ctx* ctx);
 
-/* Fluid grid: cells[n_snap][n2][n1][4] = {n_e [cm^-3], Theta_e, B [G], Omega [1/M]} at cell
- * centres of a grid uniform in x1 = ln r over [ln r_in, ln r_out] and in x2 over [0, 1],
- * theta(x2) = pi x2 + (1 - hslope)/2 sin(2 pi x2) (appendix KS-MKS).  Snapshot s is at
- * coordinate time t0 + s dt_snap.  mod_amp, mod_phase describe an analytic azimuthal
- * modulation of n_e, 1 + mod_amp sum_{m=1..4} cos(m (phi - Omega_K(r) t_s) + mod_phase[m-1])
- * with Omega_K = 1/(r^1.5 + a_gen); mod_amp = 0 disables it.  Requires n1, n2 >= 2,
- * n_snap >= 1, 0 < r_in < r_out, 0 < hslope <= 1, dt_snap > 0 when n_snap > 1, and dtype
- * RAPTOR_F32 or RAPTOR_F64.  `cells` is host memory and is copied. */
+/* Fluid grid: cells[n_snap][n2][n1][4] at cell centres of a grid uniform in x1 = ln r over
+ * [ln r_in, ln r_out] and in x2 over [0, 1], theta(x2) = pi x2 + (1 - hslope)/2 sin(2 pi x2)
+ * (appendix KS-MKS).  Snapshot s is at coordinate time t0 + s dt_snap.  mod_amp, mod_phase
+ * describe an analytic azimuthal modulation of the density field (field 0),
+ * 1 + mod_amp sum_{m=1..4} cos(m (phi - Omega_K(r) t_s) + mod_phase[m-1]) with
+ * Omega_K = 1/(r^1.5 + a_gen); mod_amp = 0 disables it.  Requires n1, n2 >= 2, n_snap >= 1,
+ * 0 < r_in < r_out, 0 < hslope <= 1, dt_snap > 0 when n_snap > 1, and dtype RAPTOR_F32 or
+ * RAPTOR_F64.  `cells` is host memory and is copied.
+ *
+ * units = RAPTOR_UNITS_CGS: the fields are {n_e [cm^-3], Theta_e, B [G], Omega [1/M]}.
+ * units = RAPTOR_UNITS_CODE: the fields are GRMHD primitives in geometrized code units
+ * {rho, u (internal energy density), b (field strength, P_mag = b^2/2), Omega [1/M]}
+ * (Sec. 4.2.2 and the electron model of Sec. 5).  Each sample interpolates the primitives and
+ * converts them with the mass unit mass_unit_g (the model's free parameter M) and the black
+ * hole's mass (opts->mass_msun, which sets L = GM/c^2): rho0 = M / L^3,
+ * n_e = rho rho0 / (m_e + m_p), B = b c sqrt(4 pi rho0); the proton-to-electron temperature
+ * ratio R = R_low / (1 + beta^2) + R_high beta^2 / (1 + beta^2), beta = (gamma_ad - 1) u /
+ * (b^2 / 2); Theta_e = (m_p / m_e) (gamma_ad - 1) (u / rho) / (1 + R).  Requires
+ * mass_unit_g > 0, r_low > 0, r_high > 0 and 1 < gamma_ad <= 2 (ignored for CGS grids). */
+enum { RAPTOR_UNITS_CGS = 0, RAPTOR_UNITS_CODE = 1 };
 typedef struct {
     int32_t n1, n2, n_snap, dtype;
     double r_in, r_out, hslope, a_gen, t0, dt_snap;
     double mod_amp, mod_phase[4];
     const void* cells;
+    int32_t units, reserved;
+    double mass_unit_g, r_low, r_high, gamma_ad;
 } raptor_grid_desc;
 
 raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* desc, raptor_grid** out);

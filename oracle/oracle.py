@@ -27,7 +27,9 @@ class Grid(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n_snap", C.c_int32), ("is_f64", C.c_int32),
                 ("r_in", C.c_double), ("r_out", C.c_double), ("hslope", C.c_double), ("a_gen", C.c_double),
                 ("t0", C.c_double), ("dt_snap", C.c_double), ("mod_amp", C.c_double),
-                ("mod_phase", C.c_double * 4), ("cells", C.c_void_p)]
+                ("mod_phase", C.c_double * 4), ("cells", C.c_void_p), ("units", C.c_int32),
+                ("reserved", C.c_int32), ("mass_unit_g", C.c_double), ("r_low", C.c_double),
+                ("r_high", C.c_double), ("gamma_ad", C.c_double)]
 
 
 class Opts(C.Structure):
@@ -85,6 +87,8 @@ def lib():
         L.orc_grid_sample.argtypes = [C.POINTER(Grid), C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, DP]
         L.orc_grid_sample.restype = C.c_int
+        L.orc_code_to_cgs.argtypes = [C.POINTER(Grid), C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_code_to_cgs.restype = None
         L.orc_fluid_frame.argtypes = [C.c_double, C.c_double, DP, DP, C.c_double, DP, DP, DP, DP]
         L.orc_fluid_frame.restype = C.c_int
         L.orc_bessel_k2.argtypes = [C.c_double]
@@ -136,7 +140,9 @@ class GridHandle:
         self.cells = np.ascontiguousarray(g.cells)
         ph = (C.c_double * 4)(*g.mod_phase)
         self.s = Grid(g.n1, g.n2, g.n_snap, 1 if self.cells.dtype == np.float64 else 0, g.r_in, g.r_out,
-                      g.hslope, g.a_gen, g.t0, g.dt_snap, g.mod_amp, ph, self.cells.ctypes.data)
+                      g.hslope, g.a_gen, g.t0, g.dt_snap, g.mod_amp, ph, self.cells.ctypes.data,
+                      getattr(g, "units", 0), 0, getattr(g, "mass_unit_g", 0.0), getattr(g, "r_low", 1.0),
+                      getattr(g, "r_high", 1.0), getattr(g, "gamma_ad", 13.0 / 9.0))
 
 
 def make_opts(eps=0.05, r_stop_factor=1.01, max_steps=10000, closure=EXACT, slow_light=0,
@@ -249,6 +255,13 @@ def mks_x2(h, th):
     it = C.c_int()
     x = lib().orc_mks_x2(h, th, C.byref(it))
     return x, it.value
+
+
+def code_to_cgs(grid_handle, prim, mass_msun=4.5e6):
+    """{rho, u, b, Omega} in code units -> {n_e, Theta_e, B, Omega} (orc_code_to_cgs)."""
+    out = np.zeros(4)
+    lib().orc_code_to_cgs(C.byref(grid_handle.s), mass_msun, _dp(_f64(prim, 4)), _dp(out))
+    return out
 
 
 def grid_sample(grid_handle, r, th, ph=0.0, t=0.0, slow_light=0, t_frame=0.0):

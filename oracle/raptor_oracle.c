@@ -33,6 +33,7 @@
 #define O_ME    9.1093837015e-28
 #define O_H     6.62607015e-27
 #define O_KB    1.380649e-16
+#define O_MP    1.67262192369e-24
 
 #define IDX(a, b) ((a) * 4 + (b))
 
@@ -584,6 +585,36 @@ int orc_grid_sample(const orc_grid* g, int slow_light, double t_frame, double r,
     return 1;
 }
 
+/* GRMHD code units (Sec. 4.2.2): the density scale rho0 = M / L^3 with L = G M_bh / c^2 and
+ * the mass unit M (the model's free parameter), the field scale B0 = c sqrt(4 pi rho0), and
+ * n_e = rho rho0 / (m_e + m_p).  Electron temperature (Sec. 5): the proton-to-electron
+ * temperature ratio R = R_low / (1 + beta_p^2) + R_high beta_p^2 / (1 + beta_p^2) with the
+ * plasma beta beta_p = P_gas / P_mag, P_mag = b^2 / 2 and, for an ideal gas of adiabatic
+ * index gamma, P_gas = (gamma - 1) u.  Reading (the paper does not print it): the gas
+ * pressure is shared by protons and electrons, P_gas = n k (T_p + T_e), so that
+ * Theta_e = k T_e / (m_e c^2) = (m_p / m_e) (P_gas / rho) / (1 + R) in code units.  b = 0
+ * means beta_p infinite (R = R_high); no density or no internal energy means Theta_e = 0. */
+void orc_code_to_cgs(const orc_grid* g, double mass_msun, const double prim[4], double out[4])
+{
+    double L = orc_length_unit(mass_msun);
+    double rho0 = g->mass_unit_g / (L * L * L);
+    double B0 = O_C * sqrt(4.0 * M_PI * rho0);
+    double rho = prim[0], u = prim[1], b = prim[2];
+    double pgas = (g->gamma_ad - 1.0) * u;
+    double pmag = 0.5 * b * b;
+    double R;
+    if (pmag > 0.0) {
+        double beta = pgas / pmag;
+        R = g->r_low / (1.0 + beta * beta) + g->r_high * beta * beta / (1.0 + beta * beta);
+    } else {
+        R = g->r_high;
+    }
+    out[0] = rho * rho0 / (O_ME + O_MP);
+    out[1] = (rho > 0.0 && u > 0.0) ? (O_MP / O_ME) * (pgas / rho) / (1.0 + R) : 0.0;
+    out[2] = b * B0;
+    out[3] = prim[3];
+}
+
 /* ===================================================================================== */
 /* Fluid frame and closure                                                              */
 /* ===================================================================================== */
@@ -725,6 +756,10 @@ void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* 
         if (status != ORC_RUNNING) break;
         double fl[4];
         if (!orc_grid_sample(grid, o->slow_light, cam->t_frame, y[1], y[2], y[3], y[0], fl)) continue;
+        if (grid->units == 1) {
+            double prim[4] = {fl[0], fl[1], fl[2], fl[3]};
+            orc_code_to_cgs(grid, o->mass_msun, prim, fl);
+        }
         double u[4], b[4], nr, cb;
         orc_fluid_frame(a, M, y, y + 4, fl[3], u, b, &nr, &cb);
         ++samples;

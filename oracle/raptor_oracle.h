@@ -26,6 +26,10 @@ typedef struct {
     double r_in, r_out, hslope, a_gen, t0, dt_snap;
     double mod_amp, mod_phase[4];
     const void* cells;               /* [n_snap][n2][n1][4] = {n_e, Theta_e, B, Omega} */
+    /* units = 1: the cells hold GRMHD primitives {rho, u, b, Omega} in code units, converted at
+     * each sample with the mass unit and the R_low / R_high electron model */
+    int32_t units, reserved;
+    double mass_unit_g, r_low, r_high, gamma_ad;
 } orc_grid;
 
 enum { ORC_CLOSURE_EXACT = 0, ORC_CLOSURE_K2_PAPER = 1, ORC_CLOSURE_CONST = 2 };
@@ -80,6 +84,9 @@ void orc_camera_ray(const orc_camera* cam, double M, double alpha, double beta,
 
 /* grid --------------------------------------------------------------------------------- */
 double orc_mks_x2(double hslope, double th, int* iters);
+/* code-unit primitives {rho, u, b, Omega} -> {n_e, Theta_e, B, Omega} for a black hole of
+ * mass_msun solar masses (Sec. 4.2.2 scaling, Sec. 5 temperature-ratio model) */
+void orc_code_to_cgs(const orc_grid* g, double mass_msun, const double prim[4], double out[4]);
 int  orc_grid_sample(const orc_grid* g, int slow_light, double t_frame, double r, double th,
                      double ph, double t, double out[4]);
 

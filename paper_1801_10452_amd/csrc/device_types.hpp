@@ -13,6 +13,13 @@ struct DevGrid {
     int n1, n2, n_snap, is_f64;
     double lnr_in, inv_d1, r_in, r_out, hslope, a_gen, t0, dt_snap, inv_dt, mod_amp;
     double mod_cos[4], mod_sin[4];   // cos / sin of the modulation phases
+    // GRMHD code units (units = 1): per-call scales (they depend on the black hole's mass) and
+    // the electron model
+    int units, pad2;
+    double ne_scale;                 // rho0 / (m_e + m_p): n_e per unit code density
+    double b_scale;                  // c sqrt(4 pi rho0): gauss per unit code field
+    double r_low, r_high, gam1;      // temperature-ratio model, gamma_ad - 1
+    double thetae_fac;               // (m_p / m_e) (gamma_ad - 1)
 };
 
 // One image of a launch.  Rays are numbered tile by tile (64 rays per tile, 8 x 8 pixels by

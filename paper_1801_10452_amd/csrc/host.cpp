@@ -335,7 +335,15 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     }
     if (tiles >= (1ll << 31) - 1) return fail(ctx, RAPTOR_E_RANGE, "too many pixels in one call");
     std::vector<DevGrid> grids(gl.size());
-    for (size_t i = 0; i < gl.size(); ++i) grids[i] = gl[i]->d;
+    for (size_t i = 0; i < gl.size(); ++i) {
+        grids[i] = gl[i]->d;
+        if (grids[i].units) {
+            // code-unit scales of this call's black-hole mass: rho0 = M / L^3
+            const double rho0 = gl[i]->mass_unit_g / (Lu * Lu * Lu);
+            grids[i].ne_scale = rho0 / (pl::ME_CGS + pl::MP_CGS);
+            grids[i].b_scale = kC * std::sqrt(4.0 * kPi * rho0);
+        }
+    }
 
     // ---- device buffers
     RAPTOR_CK(ctx->jobs.reserve(nj), "allocating the job table");
@@ -576,6 +584,12 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
     if (d->n_snap > 1 && !finite_pos(d->dt_snap)) return fail(ctx, RAPTOR_E_INVALID, "dt_snap must be > 0");
     if (!std::isfinite(d->t0) || !std::isfinite(d->mod_amp) || !std::isfinite(d->a_gen))
         return fail(ctx, RAPTOR_E_INVALID, "t0, mod_amp and a_gen must be finite");
+    if (d->units != RAPTOR_UNITS_CGS && d->units != RAPTOR_UNITS_CODE)
+        return fail(ctx, RAPTOR_E_INVALID, "units must be RAPTOR_UNITS_CGS or RAPTOR_UNITS_CODE");
+    if (d->units == RAPTOR_UNITS_CODE &&
+        !(finite_pos(d->mass_unit_g) && finite_pos(d->r_low) && finite_pos(d->r_high) && d->gamma_ad > 1.0 &&
+          d->gamma_ad <= 2.0))
+        return fail(ctx, RAPTOR_E_INVALID, "code units need mass_unit_g, r_low, r_high > 0 and 1 < gamma_ad <= 2");
     *out = nullptr;
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
     const size_t cell = d->dtype == RAPTOR_F64 ? 4 * sizeof(double) : 4 * sizeof(float);
@@ -642,6 +656,14 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
     for (int m = 0; m < 4; ++m) {
         G.mod_cos[m] = std::cos(d->mod_phase[m]);
         G.mod_sin[m] = std::sin(d->mod_phase[m]);
+    }
+    G.units = d->units;
+    if (d->units == RAPTOR_UNITS_CODE) {
+        g->mass_unit_g = d->mass_unit_g;
+        G.r_low = d->r_low;
+        G.r_high = d->r_high;
+        G.gam1 = d->gamma_ad - 1.0;
+        G.thetae_fac = pl::MP_CGS / pl::ME_CGS * G.gam1;
     }
     g->owner = ctx;
     ctx->live.push_back(g);

@@ -10,6 +10,7 @@ constexpr double C_LIGHT = 2.99792458e10;
 constexpr double Q_E = 4.80320471e-10;
 constexpr double ME_CGS = 9.1093837015e-28;
 constexpr double H_PLANCK = 6.62607015e-27;
+constexpr double MP_CGS = 1.67262192369e-24;
 constexpr double PI_D = 3.14159265358979323846;
 constexpr double NUC_PER_GAUSS = Q_E / (2.0 * PI_D * ME_CGS * C_LIGHT);      // e/(2 pi m_e c)
 constexpr double J_PREF = 1.4142135623730951 * PI_D * Q_E * Q_E / (3.0 * C_LIGHT);  // sqrt2 pi e^2/(3c)
@@ -124,8 +125,28 @@ __device__ inline double x2_start(const DevGrid& g, double th)
 
 __device__ inline bool in_plasma(const DevGrid& g, double r) { return r >= g.r_in && r <= g.r_out; }
 
+// GRMHD primitives {rho, u, b, Omega} in code units -> {n_e, Theta_e, B, Omega} (Sec. 4.2.2:
+// n_e = rho rho0 / (m_e + m_p), B = b B0 with B0 = c sqrt(4 pi rho0); Sec. 5: the proton-to-
+// electron temperature ratio R = R_low / (1 + beta^2) + R_high beta^2 / (1 + beta^2) with
+// beta = P_gas / P_mag, P_gas = (gamma - 1) u, P_mag = b^2 / 2; Theta_e = (m_p / m_e) P_gas /
+// rho / (1 + R), the gas pressure shared by ions and electrons).  R is formed as
+// (R_low P_mag^2 + R_high P_gas^2) / (P_mag^2 + P_gas^2), finite for b = 0; a cell without
+// density or pressure has Theta_e = 0 (no emission).
+__device__ inline void code_to_cgs(const DevGrid& g, double v[4])
+{
+    const double rho = v[0], pg = g.gam1 * v[1], pm = 0.5 * v[2] * v[2];
+    const double pg2 = pg * pg, pm2 = pm * pm;
+    const double den = pm2 + pg2;
+    const double R = den > 0.0 ? (g.r_low * pm2 + g.r_high * pg2) * rt::rcp_nr(den) : g.r_high;
+    const double the = (rho > 0.0 && v[1] > 0.0) ? g.thetae_fac * v[1] * rt::rcp_nr(rho * (1.0 + R)) : 0.0;
+    v[0] = rho * g.ne_scale;
+    v[1] = the;
+    v[2] = v[2] * g.b_scale;
+}
+
 // Fluid quantities {n_e, Theta_e, B, Omega} at the ray point y = (t, r, theta, phi); the caller
-// has checked that r lies in the grid's radial range.
+// has checked that r lies in the grid's radial range.  A code-unit grid is interpolated in its
+// primitives and converted at the sample point.
 __device__ inline void sample_fluid(const DevGrid& g, int slow_light, int fast_snap, const double* y, double out[4])
 {
     const double r = y[1];
@@ -161,6 +182,7 @@ __device__ inline void sample_fluid(const DevGrid& g, int slow_light, int fast_s
 #pragma unroll
         for (int f = 0; f < 4; ++f) out[f] = v0[f];
     }
+    if (g.units) code_to_cgs(g, out);
 }
 
 // Fluid frame of a circular flow u = u^t (1, 0, 0, Omega) in the KS metric, with the ZAMO

@@ -20,6 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 CLOSURE_EXACT, CLOSURE_K2_PAPER, CLOSURE_CONST, CLOSURE_MLP, CLOSURE_MLP_BF16 = 0, 1, 2, 3, 4
 MLP_SPLIT, MLP_BF16, MLP_F32 = 0, 1, 2
 LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
+UNITS_CGS, UNITS_CODE = 0, 1
 RK4, RK2, VERLET, VERLET_CORRECTED = 0, 1, 2, 3
 MLP_PARAMS = 12866
 RAY_HORIZON, RAY_ESCAPED, RAY_MAXSTEP, RAY_NUMERIC = 1, 2, 3, 4
@@ -44,7 +45,8 @@ class CGridDesc(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n_snap", C.c_int32), ("dtype", C.c_int32),
                 ("r_in", C.c_double), ("r_out", C.c_double), ("hslope", C.c_double), ("a_gen", C.c_double),
                 ("t0", C.c_double), ("dt_snap", C.c_double), ("mod_amp", C.c_double), ("mod_phase", C.c_double * 4),
-                ("cells", C.c_void_p)]
+                ("cells", C.c_void_p), ("units", C.c_int32), ("reserved", C.c_int32),
+                ("mass_unit_g", C.c_double), ("r_low", C.c_double), ("r_high", C.c_double), ("gamma_ad", C.c_double)]
 
 
 class COpts(C.Structure):
@@ -263,7 +265,9 @@ class Context:
     def upload_grid(self, g) -> GridHandle:
         cells = np.ascontiguousarray(g.cells)
         d = CGridDesc(g.n1, g.n2, g.n_snap, F64 if cells.dtype == np.float64 else F32, g.r_in, g.r_out, g.hslope,
-                      g.a_gen, g.t0, g.dt_snap, g.mod_amp, (C.c_double * 4)(*g.mod_phase), cells.ctypes.data)
+                      g.a_gen, g.t0, g.dt_snap, g.mod_amp, (C.c_double * 4)(*g.mod_phase), cells.ctypes.data,
+                      getattr(g, "units", UNITS_CGS), 0, getattr(g, "mass_unit_g", 0.0), getattr(g, "r_low", 1.0),
+                      getattr(g, "r_high", 1.0), getattr(g, "gamma_ad", 13.0 / 9.0))
         h = C.c_void_p()
         self._check(lib().raptor_grid_upload(self.h, C.byref(d), C.byref(h)))
         gh = GridHandle(h.value, self)

@@ -48,6 +48,12 @@ class Grid:
     dt_snap: float = 10.0
     mod_amp: float = 0.0
     mod_phase: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0, 0.0])
+    # GRMHD code units (units = 1): fields {rho, u, b, Omega}; the mass unit and electron model
+    units: int = 0
+    mass_unit_g: float = 0.0
+    r_low: float = 1.0
+    r_high: float = 1.0
+    gamma_ad: float = 13.0 / 9.0
 
     @property
     def n_snap(self):
@@ -111,11 +117,41 @@ def make_grid(n1=256, n2=256, a_gen=0.9375, dtype=np.float32, seed=S0, r_in=1.1,
                 dt_snap=dt_snap, mod_amp=mod_amp, mod_phase=phase)
 
 
-def constant_grid(value, n1=8, n2=8, r_in=1.1, r_out=50.0, hslope=0.3, dtype=np.float64, a_gen=0.0):
-    """A grid whose four fields are the constants ``value = (n_e, Theta_e, B, Omega)``."""
+def constant_grid(value, n1=8, n2=8, r_in=1.1, r_out=50.0, hslope=0.3, dtype=np.float64, a_gen=0.0, **units):
+    """A grid whose four fields are the constants ``value`` ((n_e, Theta_e, B, Omega), or code-unit
+    primitives (rho, u, b, Omega) with units=1 and the model keywords)."""
     cells = np.empty((1, n2, n1, 4), dtype=dtype)
     cells[...] = np.asarray(value, dtype=dtype)
-    return Grid(cells=cells, r_in=r_in, r_out=r_out, hslope=hslope, a_gen=a_gen)
+    return Grid(cells=cells, r_in=r_in, r_out=r_out, hslope=hslope, a_gen=a_gen, **units)
+
+
+def torus_snapshot_code(n1, n2, a_gen, seed, r_in=1.1, r_out=50.0, hslope=0.3, noise=0.1, gamma_ad=13.0 / 9.0):
+    """One snapshot [n2][n1][4] of GRMHD primitives in code units, float64:
+    rho = (r/r_h)^-1.5 exp(-cos^2 theta / (2 * 0.3^2)) (1 + noise U(-1,1)); u = 0.1 rho r_h / r;
+    plasma beta 0.1 + 30 exp(-cos^2 theta / (2 * 0.3^2)) (magnetized funnel, weakly magnetized
+    disk), b = sqrt(2 (gamma_ad - 1) u / beta); Omega = 1 / (r^1.5 + a_gen)."""
+    r1, th1 = cell_centres(n1, n2, r_in, r_out, hslope)
+    th, r = np.meshgrid(th1, r1, indexing="ij")
+    rh = 1.0 + np.sqrt(1.0 - a_gen * a_gen)
+    un = uniform_stream(seed, n1 * n2).reshape(n2, n1)
+    disk = np.exp(-np.cos(th) ** 2 / (2 * 0.3 ** 2))
+    rho = (r / rh) ** -1.5 * disk * (1.0 + noise * (2.0 * un - 1.0))
+    u = 0.1 * rho * rh / r
+    beta_p = 0.1 + 30.0 * disk
+    b = np.sqrt(2.0 * (gamma_ad - 1.0) * u / beta_p)
+    omega = 1.0 / (r ** 1.5 + a_gen)
+    return np.stack([rho, u, b, omega], axis=-1)
+
+
+def make_code_grid(n1=256, n2=256, a_gen=0.9375, dtype=np.float32, seed=S0 + 300, r_in=1.1, r_out=50.0,
+                   hslope=0.3, n_snap=1, t0=0.0, dt_snap=10.0, noise=0.1, mass_unit_g=5e17, r_low=1.0,
+                   r_high=10.0, gamma_ad=13.0 / 9.0) -> Grid:
+    """A code-unit grid (units = 1) of the recipe in torus_snapshot_code; the mass unit 5e17 g
+    gives electron densities near those of the CGS recipe for M = 4.5e6 solar masses."""
+    snaps = [torus_snapshot_code(n1, n2, a_gen, seed + s, r_in, r_out, hslope, noise, gamma_ad) for s in range(n_snap)]
+    cells = np.ascontiguousarray(np.stack(snaps, axis=0).astype(dtype))
+    return Grid(cells=cells, r_in=r_in, r_out=r_out, hslope=hslope, a_gen=a_gen, t0=t0, dt_snap=dt_snap,
+                units=1, mass_unit_g=mass_unit_g, r_low=r_low, r_high=r_high, gamma_ad=gamma_ad)
 
 
 # --------------------------------------------------------------------------------------

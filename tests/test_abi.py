@@ -27,13 +27,34 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(R.EXPORTS) | {n for n in names if n.startswith("raptor_mlp")}
 
 
-def test_struct_sizes_match_header_layout():
+def test_struct_sizes_match_header_layout(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets a C compiler gives the
+    header's structures."""
     import ctypes
+    import subprocess
     from paper_1801_10452_amd import raptor as R
     assert ctypes.sizeof(R.CCamera) == 48
     assert ctypes.sizeof(R.COpts) == 16 + 24 + 40 + 8 + 8
-    assert ctypes.sizeof(R.CGridDesc) == 16 + 48 + 8 + 32 + 8
+    assert ctypes.sizeof(R.CGridDesc) == 16 + 48 + 8 + 32 + 8 + 8 + 32
     assert ctypes.sizeof(R.CStats) == 96
+    pairs = {"raptor_camera": R.CCamera, "raptor_opts": R.COpts, "raptor_grid_desc": R.CGridDesc,
+             "raptor_stats": R.CStats, "raptor_plan": R.CPlan}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "raptor.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in pairs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert int(got[f"{cname}.{f[0]}"]) == getattr(py, f[0]).offset, (cname, f[0])
 
 
 def test_work_per_unit_counts():
