@@ -75,6 +75,7 @@ struct raptor_grid {
     double mass_unit_g = 0.0;   // code-unit grids: the model's mass unit
     void* cells = nullptr;
     float2* x2tab = nullptr;
+    double2* x2sc = nullptr;
     raptor_ctx* owner = nullptr;
 };
 

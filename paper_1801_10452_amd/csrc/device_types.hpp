@@ -8,6 +8,7 @@
 struct DevGrid {
     const void* cells;
     const float2* x2tab;       // {x2, dx2/dtheta} at x2n uniform theta nodes on [0, pi] (start values)
+    const double2* x2sc;       // {sin, cos}(2 pi x2) of the tabulated (float) x2 of each node
     int x2n, pad;
     double x2_inv_dth, x2_dth;
     int n1, n2, n_snap, is_f64;

@@ -525,6 +525,7 @@ void raptor_destroy(raptor_ctx* ctx)
     for (raptor_grid* g : ctx->live) {
         if (g->cells) (void)hipFree(g->cells);
         if (g->x2tab) (void)hipFree(g->x2tab);
+        if (g->x2sc) (void)hipFree(g->x2sc);
         delete g;
     }
     ctx->jobs.release();
@@ -611,6 +612,7 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
     // cubic Hermite start value of the chart inversion
     const int x2n = 1024;
     std::vector<float2> x2h(x2n);
+    std::vector<double2> sch(x2n);
     for (int i = 0; i < x2n; ++i) {
         const double th = kPi * i / (x2n - 1);
         double x = th / kPi;
@@ -624,11 +626,18 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
         }
         x2h[i].x = (float)x;
         x2h[i].y = (float)(1.0 / (kPi * (1.0 + (1.0 - d->hslope) * std::cos(2.0 * kPi * x))));
+        // sin and cos of 2 pi times the stored (float) node value, for the shifted first iteration
+        const double xf = (double)x2h[i].x;
+        sch[i].x = std::sin(2.0 * kPi * xf);
+        sch[i].y = std::cos(2.0 * kPi * xf);
     }
     e = hipMalloc(&g->x2tab, x2n * sizeof(float2));
     if (e == hipSuccess) e = hipMemcpy(g->x2tab, x2h.data(), x2n * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&g->x2sc, x2n * sizeof(double2));
+    if (e == hipSuccess) e = hipMemcpy(g->x2sc, sch.data(), x2n * sizeof(double2), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (g->x2tab) (void)hipFree(g->x2tab);
+        if (g->x2sc) (void)hipFree(g->x2sc);
         (void)hipFree(g->cells);
         delete g;
         return dev_fail(ctx, e, "uploading the MKS table");
@@ -636,6 +645,7 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
     DevGrid& G = g->d;
     G.cells = g->cells;
     G.x2tab = g->x2tab;
+    G.x2sc = g->x2sc;
     G.x2n = x2n;
     G.x2_inv_dth = (x2n - 1) / kPi;
     G.x2_dth = kPi / (x2n - 1);
@@ -680,6 +690,7 @@ void raptor_grid_release(raptor_ctx* ctx, raptor_grid* g)
     (void)hipStreamSynchronize(ctx->stream);
     if (g->cells) (void)hipFree(g->cells);
     if (g->x2tab) (void)hipFree(g->x2tab);
+    if (g->x2sc) (void)hipFree(g->x2sc);
     ctx->live.erase(it);
     delete g;
 }

@@ -1,6 +1,7 @@
 // plasma.hpp -- fluid sampling, fluid frame, thermal-synchrotron closure, transfer update.
 #pragma once
 #include "device_types.hpp"
+#include "ks_geodesic.hpp"
 #include "rt_math.hpp"
 
 namespace pl {
@@ -24,26 +25,35 @@ constexpr double H_OVER_MEC2 = H_PLANCK / (ME_CGS * C_LIGHT * C_LIGHT);      // 
 // [0, 1] or the derivative vanishes.  It stops after the update that moved x2 by less than
 // 1e-6: that update leaves an error of order (1e-6)^3, i.e. x2 is converged to rounding, the
 // same root the paper's iteration converges to.
+// One Halley update of x2 at x, given s = sin(2 pi x), c = cos(2 pi x).
+template <class T>
+__host__ __device__ inline T mks_halley(T h, T th, T x, T s, T c)
+{
+    using namespace rt;
+    const T hh = T(0.5) * (T(1.0) - h);
+    const T f = T(PI_D) * x + hh * s - th;
+    const T fp = T(PI_D) * (T(1.0) + (T(1.0) - h) * c);
+    const T fpp = T(-2.0 * PI_D * PI_D) * (T(1.0) - h) * s;
+    T xn;
+    if (fabs_(fp) < T(1e-300)) {
+        xn = T(0.05);
+    } else {
+        const T den = T(2.0) * fp * fp - f * fpp;
+        xn = (den > fp * fp * T(0.5)) ? x - T(2.0) * f * fp * rcp_nr(den) : x - f * rcp_nr(fp);
+        if (xn < T(0.0) || xn > T(1.0)) xn = T(0.05);
+    }
+    return xn;
+}
+
 template <class T>
 __host__ __device__ inline T mks_x2(T h, T th, T x0)
 {
     using namespace rt;
     T x = x0;
-    const T hh = T(0.5) * (T(1.0) - h);
     for (int n = 0; n < 50; ++n) {
         T s, c;
         sincos_small(T(2.0 * PI_D) * x, &s, &c);   // x in [0, 1]: argument in [0, 2 pi]
-        const T f = T(PI_D) * x + hh * s - th;
-        const T fp = T(PI_D) * (T(1.0) + (T(1.0) - h) * c);
-        const T fpp = T(-2.0 * PI_D * PI_D) * (T(1.0) - h) * s;
-        T xn;
-        if (fabs_(fp) < T(1e-300)) {
-            xn = T(0.05);
-        } else {
-            const T den = T(2.0) * fp * fp - f * fpp;
-            xn = (den > fp * fp * T(0.5)) ? x - T(2.0) * f * fp * rcp_nr(den) : x - f * rcp_nr(fp);
-            if (xn < T(0.0) || xn > T(1.0)) xn = T(0.05);
-        }
+        const T xn = mks_halley(h, th, x, s, c);
         const T dx = fabs_(xn - x);
         x = xn;
         if (dx < T(1e-6)) break;
@@ -123,6 +133,28 @@ __device__ inline double x2_start(const DevGrid& g, double th)
     return h00 * A.x + h10 * A.y * g.x2_dth + h01 * B.x + h11 * B.y * g.x2_dth;
 }
 
+// x2(theta): the Hermite start value, then Halley's iteration (mks_x2).  The first iteration
+// takes sin and cos of 2 pi x from the table's values at the left node's x2 (stored as a
+// float, the table holds sin and cos of exactly that value) and the angle-addition shift by
+// 2 pi (x - x_node), |shift| <= 2 pi (node spacing in x2), instead of a full sine-cosine.
+__device__ inline double x2_of_theta(const DevGrid& g, double th)
+{
+    double q = ::fmin(::fmax(th * g.x2_inv_dth, 0.0), (double)(g.x2n - 1) - 1e-9);
+    const int i = (int)q;
+    const double s = q - i;
+    const float2 A = g.x2tab[i], B = g.x2tab[i + 1];
+    const double2 SC = g.x2sc[i];
+    const double s2 = s * s, s3 = s2 * s;
+    const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
+    const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
+    const double x0 = h00 * A.x + h10 * A.y * g.x2_dth + h01 * B.x + h11 * B.y * g.x2_dth;
+    double sn, cs;
+    rk::sincos_add(2.0 * PI_D * x0, 2.0 * PI_D * (x0 - (double)A.x), SC.x, SC.y, &sn, &cs);
+    const double x1 = mks_halley(g.hslope, th, x0, sn, cs);
+    if (::fabs(x1 - x0) < 1e-6) return x1;
+    return mks_x2(g.hslope, th, x1);
+}
+
 __device__ inline bool in_plasma(const DevGrid& g, double r) { return r >= g.r_in && r <= g.r_out; }
 
 // GRMHD primitives {rho, u, b, Omega} in code units -> {n_e, Theta_e, B, Omega} (Sec. 4.2.2:
@@ -151,7 +183,7 @@ __device__ inline void sample_fluid(const DevGrid& g, int slow_light, int fast_s
 {
     const double r = y[1];
     const double x1 = rt::log_pos(r);
-    const double x2 = mks_x2(g.hslope, y[2], x2_start(g, y[2]));
+    const double x2 = x2_of_theta(g, y[2]);
     double f1 = (x1 - g.lnr_in) * g.inv_d1 - 0.5;
     double f2 = x2 * g.n2 - 0.5;
     f1 = ::fmin(::fmax(f1, 0.0), (double)(g.n1 - 1));
