@@ -92,7 +92,7 @@ struct raptor_ctx {
     rctx::DevBuf<int> status, steps;
     rctx::DevBuf<unsigned int> counter;
     rctx::DevBuf<unsigned long long> stats;
-    rctx::DevBuf<double2> k2;
+    rctx::DevBuf<double4> k2;
     K2Table k2t{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // graph replay of the batch launch: a capture-only stream, the instantiated graph and the

@@ -41,7 +41,7 @@ __device__ inline void exact_targets(const K2Table& k2, double lx, double lth, d
     const double sb = ::sqrt(::fmax(1.0 - cb * cb, 0.0));
     const double ns = (2.0 / 9.0) * th * th * sb;
     const double t = ::cbrt(::exp(lx) / ns);
-    const double y = ::log(ns) - pl::ln_k2(k2, lth) + ::log(t) + 2.0 * ::log(t + pl::TWO_11_12);
+    const double y = ::log(ns) - pl::ln_k2_theta(k2, th) + ::log(t) + 2.0 * ::log(t + pl::TWO_11_12);
     *y0 = y;
     *y1 = y - 2.0 * lx - lth;
     *tc = t;

@@ -257,19 +257,22 @@ __host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T s, T c
     return zamo;
 }
 
-// ln K2(1/Theta) from the tabulated values and u-derivatives at uniform u = ln Theta nodes,
-// cubic Hermite interpolation; u is clamped to the table range.
-__device__ inline double ln_k2(const K2Table& t, double lnth)
+// ln K2(1/Theta) from the octave table: the binary exponent and mantissa of Theta select the
+// interval (no logarithm), cubic Hermite interpolation inside it.
+__host__ __device__ inline double ln_k2_theta(const K2Table& t, double the)
 {
-    double q = (lnth - t.u0) * t.inv_du;
-    q = ::fmin(::fmax(q, 0.0), (double)(t.n - 1) - 1e-9);
-    const int i = (int)q;
-    const double s = q - i;
-    const double2 A = t.tab[i], B = t.tab[i + 1];
+    const double th = ::fmin(::fmax(the, t.th_lo), t.th_hi);
+    int e;
+    const double m = __builtin_frexp(th, &e);            // th = m 2^e, m in [1/2, 1)
+    const double q = (m - 0.5) * (double)(2 * t.nsub);   // exact: a power-of-two scaling
+    int j = (int)q;
+    j = j < t.nsub - 1 ? j : t.nsub - 1;
+    const double s = q - j;
+    const double4 E = t.tab[(e - t.e_lo) * t.nsub + j];
     const double s2 = s * s, s3 = s2 * s;
     const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
     const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
-    return h00 * A.x + h10 * A.y * t.du + h01 * B.x + h11 * B.y * t.du;
+    return h00 * E.x + h10 * E.y + h01 * E.z + h11 * E.w;
 }
 
 // Emission j_nu and absorption alpha_nu in the fluid frame (Sec. 4.2.2): Leung et al. fit

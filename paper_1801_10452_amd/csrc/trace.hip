@@ -55,7 +55,7 @@ struct Transfer<double> {
         emits = (ne > 0.0 && the > 0.0 && bf > 0.0 && sinb > 0.0);
         k2_inv = 0.0;
         if (emits && p.closure != CL_CONST)
-            k2_inv = (p.closure == CL_K2_PAPER) ? 1.0 / (2.0 * the * the) : ::exp(-pl::ln_k2(p.k2, rt::log_pos(the)));
+            k2_inv = (p.closure == CL_K2_PAPER) ? 1.0 / (2.0 * the * the) : ::exp(-pl::ln_k2_theta(p.k2, the));
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
@@ -103,7 +103,7 @@ struct Transfer<float> {
         k2_inv = 0.0f;
         if (emits && p.closure != CL_CONST)
             k2_inv = (p.closure == CL_K2_PAPER) ? 1.0f / (2.0f * the * the)
-                                               : rt::exp_mixed(-pl::ln_k2(p.k2, rt::log_pos(fl[1])));
+                                               : rt::exp_mixed(-pl::ln_k2_theta(p.k2, fl[1]));
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
