@@ -763,6 +763,10 @@ void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* 
         double u[4], b[4], nr, cb;
         orc_fluid_frame(a, M, y, y + 4, fl[3], u, b, &nr, &cb);
         ++samples;
+        /* reading: a sample whose fluid-frame frequency is not positive -- possible only through
+         * integration error, for the low-order integrators in the last step before the horizon --
+         * has no defined emission or absorption and adds nothing */
+        if (!(nr > 0.0)) continue;
         double ds = nr * fabs(dl) * Lu;
         for (int f = 0; f < n_nu; ++f) {
             double jv, av;

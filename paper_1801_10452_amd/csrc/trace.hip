@@ -214,14 +214,19 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
     pl::sample_fluid(G, p.slow_light, li.fast_snap, y, fl);
     double nr, cb;
     const bool zamo = pl::fluid_frame(li.a, li.a * li.a, p.M, y, q[8], q[9], fl[3], &nr, &cb);
-    Transfer<TT> tr;
-    tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
 #pragma unroll
     for (int f = 0; f < NNU; ++f) {
         A[f] = 0.0;
         dtau[f] = 0.0;
-        if (f < li.n_nu) tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
     }
+    // a sample whose fluid-frame frequency is not positive (integration error of a low-order
+    // integrator in the last step before the horizon) has no defined emission: it adds nothing
+    if (!(nr > 0.0)) return zamo;
+    Transfer<TT> tr;
+    tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+#pragma unroll
+    for (int f = 0; f < NNU; ++f)
+        if (f < li.n_nu) tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
     return zamo;
 }
 
@@ -243,7 +248,9 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
         const double y[8] = {q[0], q[1], q[2], q[3], q[4], q[5], 0.0, q[6]};
         pl::sample_fluid(G, p.slow_light, li.fast_snap, y, fl);
         zamo = pl::fluid_frame(li.a, li.a * li.a, p.M, y, q[8], q[9], fl[3], &nr, &cb);
-        tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+        // a non-positive fluid-frame frequency has no defined emission (see eval_sample): the
+        // transfer stays non-emitting and the sample adds nothing
+        if (nr > 0.0) tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
     }
     c_zamo += __popcll(__ballot(zamo));
     const double nuc = pl::NUC_PER_GAUSS * fl[2];
@@ -652,7 +659,7 @@ __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* sta
 
 int kernel_wpe(int wpe, bool mlpc, int integ)
 {
-    if (integ != INTEG_RK4) return 2;   // RK2 and Verlet are instantiated for two waves per SIMD only
+    if (integ != INTEG_RK4) return wpe >= 3 ? 3 : 2;   // RK2 and Verlet: two or three waves per SIMD
     if (mlpc) return wpe >= 2 ? 2 : 1;
     return wpe >= 3 ? 3 : wpe == 2 ? 2 : 1;
 }
@@ -663,9 +670,12 @@ template <int NNU, class TT>
 const void* symbol_of(int wpe, bool mlpc, int integ)
 {
     const int w = kernel_wpe(wpe, mlpc, integ);
-    if (integ == INTEG_RK2) return (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK2>;
+    if (integ == INTEG_RK2)
+        return w == 3 ? (const void*)trace_kernel<NNU, TT, 3, false, INTEG_RK2>
+                      : (const void*)trace_kernel<NNU, TT, 2, false, INTEG_RK2>;
     if (integ == INTEG_VERLET || integ == INTEG_VERLET_CORR)
-        return (const void*)trace_kernel<NNU, TT, 2, false, INTEG_VERLET>;
+        return w == 3 ? (const void*)trace_kernel<NNU, TT, 3, false, INTEG_VERLET>
+                      : (const void*)trace_kernel<NNU, TT, 2, false, INTEG_VERLET>;
     if (mlpc)
         return w == 2 ? (const void*)trace_kernel<NNU, TT, 2, true, INTEG_RK4>
                       : (const void*)trace_kernel<NNU, TT, 1, true, INTEG_RK4>;

@@ -129,3 +129,31 @@ def test_light_curve_batch(R, ctx, orc):
     assert worst <= TOL
     assert np.all(np.abs(rel) < 0.5) and np.abs(rel).max() > 1e-6   # slow light changes the curve
     ctx.release_grid(gh)
+
+
+@pytest.mark.parametrize("integ", ["RK4", "RK2", "VERLET", "VERLET_CORRECTED"])
+def test_integrators_production_batch(R, ctx, orc, integ):
+    """The production batch (9 x 512^2, 230 GHz, FP32 transfer) with each integrator of
+    Sec. 2.2: throughput, and sampled pixels against the oracle's same integrator."""
+    sets = S.production_set()
+    hs = {}
+    for _, g in sets:
+        if id(g) not in hs:
+            hs[id(g)] = ctx.upload_grid(g)
+    cams = [c for c, _ in sets]
+    opts = R.default_opts(transfer_prec=R.F32, integrator=getattr(R, integ))
+    ctx.trace_batch(cams, [hs[id(g)] for _, g in sets], [S.NU_230], opts)   # warm-up
+    imgs, flux, st = ctx.trace_batch(cams, [hs[id(g)] for _, g in sets], [S.NU_230], opts)
+    print(f"[integrator {integ}] 9 x 512^2: kernel_ms {st.kernel_ms:.2f}, ray_steps {st.ray_steps}, "
+          f"{st.ray_steps / st.kernel_ms * 1e3:.3e} ray-steps/s, {9 / st.kernel_ms * 1e3:.0f} images/s", flush=True)
+    from paper_1801_10452_amd.raptor import split_batch_images
+    parts = split_batch_images(imgs, cams, 1)
+    worst = 0.0
+    for k, (c, g) in enumerate(sets):
+        pix = sample_pixels(c, 4, seed=S.S0 + 900 + k)
+        worst = max(worst, sampled_errors(orc, c, g, opts, [S.NU_230], parts[k], pix))
+    print(f"[integrator {integ}] 36 sampled pixels: worst rel err {worst:.3e}", flush=True)
+    assert st.n_numeric == 0 and worst <= TOL
+    assert np.isfinite(imgs).all() and (imgs >= 0).all() and np.isfinite(flux).all()
+    for h in hs.values():
+        ctx.release_grid(h)

@@ -101,3 +101,23 @@ def test_verlet_step_reuses_the_derivative(orc):
     assert np.allclose(yn[:4], xp, rtol=1e-15, atol=0)
     assert np.allclose(acc, fp[4:], rtol=1e-13, atol=0)
     assert np.allclose(yn[4:], y[4:] + 0.5 * (f0[4:] + fp[4:]) * dl, rtol=1e-13, atol=0)
+
+
+def test_verlet_last_step_before_horizon_adds_nothing_undefined(orc):
+    """Velocity Verlet's last step before the horizon can leave a wave vector whose fluid-frame
+    frequency is negative (a = 0, i = 30 deg, a ray aimed at the hole at 512^2).  That sample
+    has no defined emission: it is counted and adds nothing, so the intensity stays the finite
+    sum of the earlier samples."""
+    import math
+    import synthetic as S
+    c, g = S.production_set()[0]
+    assert c.spin == 0.0 and c.incl_deg == 30.0
+    opts = orc.make_opts(integrator=orc.VERLET)
+    al, be = orc.pixel_alpha_beta(c, 254, 235)
+    I, info, rec = orc.trace_ray(c, orc.GridHandle(g), opts, al, be, [230e9], record=4000)
+    steps = [rec[i] for i in range(info.steps)]
+    assert info.status == orc.HORIZON
+    assert math.isfinite(I[0]) and I[0] > 0.0
+    # the recorded samples all have positive fluid-frame frequencies; one step was sampled-but-skipped
+    nus = [r.nu_r for r in steps if r.sampled]
+    assert all(v > 0.0 for v in nus) and info.samples == len(nus) + 1
