@@ -8,6 +8,8 @@
 Per sampled pixel and frequency the relative error against the oracle is bounded by 1e-6
 (floor 1e-10 of the image maximum at that frequency), for the FP64 and FP32 transfer forms.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -157,3 +159,31 @@ def test_integrators_production_batch(R, ctx, orc, integ):
     assert np.isfinite(imgs).all() and (imgs >= 0).all() and np.isfinite(flux).all()
     for h in hs.values():
         ctx.release_grid(h)
+
+
+@pytest.mark.parametrize("nu_set", ["1GHz", "24"])
+def test_tau_cutoff_full_size(R, ctx, orc, slow_set, nu_set):
+    """Optical-depth cut-off (ln 1000) on the 256^2 spectrum camera, fast light: at 1 GHz (an
+    opaque core) and over the 24 frequencies (a ray stops only when opaque at all of them).
+    Timing with and without the cut, the flux-level difference (the lost emission is below
+    e^-tau_cut of each stopped ray's source function), and sampled pixels against the oracle."""
+    cam, grid, nu24 = slow_set
+    nu = [1e9] if nu_set == "1GHz" else nu24
+    gh = ctx.upload_grid(grid)
+    base = R.default_opts(transfer_prec=R.F32)
+    cut = R.default_opts(transfer_prec=R.F32, tau_cutoff=math.log(1000.0))
+    ctx.trace_spectrum(cam, gh, nu, cut)   # warm-up
+    i0, f0, s0 = ctx.trace_spectrum(cam, gh, nu, base)
+    i1, f1, s1 = ctx.trace_spectrum(cam, gh, nu, cut)
+    f0, f1 = np.asarray(f0), np.asarray(f1)
+    rel = np.abs(f1 / f0 - 1.0)
+    print(f"[tau cutoff {nu_set}] no cut {s0.kernel_ms:.2f} ms {s0.ray_steps} steps; cut {s1.kernel_ms:.2f} ms "
+          f"{s1.ray_steps} steps, {s1.n_opaque} opaque rays; max |dF/F| {rel.max():.3e}", flush=True)
+    assert s1.ray_steps <= s0.ray_steps and rel.max() <= 1e-3
+    if nu_set == "1GHz":
+        assert s1.n_opaque > 1000 and s1.ray_steps < s0.ray_steps
+    pix = sample_pixels(cam, 10, seed=S.S0 + 950)
+    worst = sampled_errors(orc, cam, grid, cut, nu, i1, pix)
+    print(f"[tau cutoff {nu_set}] sampled worst rel err {worst:.3e}", flush=True)
+    assert worst <= TOL
+    ctx.release_grid(gh)
