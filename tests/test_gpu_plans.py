@@ -1,0 +1,85 @@
+"""Launch plans and the autotuner (scheduling row of the path): every plan of the search space
+-- work-group size, tile width, refill threshold, work-groups per CU and the waves-per-SIMD
+variant, which also sets the depth of the LDS sample queue -- gives the same images bit for bit
+for every integrator and both transfer precisions; the autotuner installs a plan that is no
+slower than the default and leaves the images unchanged."""
+import numpy as np
+import pytest
+
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+
+PLANS = [dict(), dict(threads=64), dict(threads=128, tile_width=16), dict(tile_width=64, refill_threshold=32),
+         dict(min_waves_per_simd=1), dict(min_waves_per_simd=2, blocks_per_cu=1),
+         dict(min_waves_per_simd=3, refill_threshold=8, tile_width=32), dict(threads=512, blocks_per_cu=4)]
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1801_10452_amd import raptor
+    return raptor
+
+
+@pytest.fixture
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("integ", ["RK4", "RK2", "VERLET"])
+def test_every_plan_gives_the_same_images(R, ctx, prec, integ):
+    cam = S.Camera(spin=0.9375, incl_deg=60.0, nx=96, ny=72)   # tiles of every width end ragged
+    grid = S.make_grid(128, 128, a_gen=0.9375, dtype=np.float64)
+    gh = ctx.upload_grid(grid)
+    nu = S.NU_VLBI
+    tp = R.F32 if prec == "f32" else R.F64
+    opts = R.default_opts(transfer_prec=tp, integrator=getattr(R, integ))
+    ref = None
+    for pl in PLANS:
+        R.set_plan(ctx, len(nu), tp, R.make_plan(**pl))
+        img, flux, st = ctx.trace_spectrum(cam, gh, nu, opts)
+        if ref is None:
+            ref, ref_flux, ref_st = img.copy(), np.array(flux), st
+            assert np.abs(ref).max() > 0
+            continue
+        diff = np.abs(img - ref).max()
+        print(f"[plans {integ} {prec}] {pl}: max |diff| {diff:.3e}, kernel_ms {st.kernel_ms:.3f}", flush=True)
+        assert np.array_equal(img, ref) and np.array_equal(np.array(flux), ref_flux), pl
+        assert (st.ray_steps, st.samples, st.rays) == (ref_st.ray_steps, ref_st.samples, ref_st.rays)
+    ctx.release_grid(gh)
+
+
+def test_invalid_plans_are_refused(R, ctx):
+    for bad in (dict(threads=96), dict(tile_width=12), dict(min_waves_per_simd=4), dict(refill_threshold=0),
+                dict(blocks_per_cu=-1)):
+        with pytest.raises(R.RaptorError) as e:
+            R.set_plan(ctx, 1, R.F32, R.make_plan(**bad))
+        assert e.value.status == R.E_INVALID
+
+
+def test_autotuner_installs_a_plan_no_slower_and_images_unchanged(R, ctx):
+    sets = S.production_set(res=256)
+    hs = {}
+    for _, g in sets:
+        if id(g) not in hs:
+            hs[id(g)] = ctx.upload_grid(g)
+    cams = [c for c, _ in sets]
+    grids = [hs[id(g)] for _, g in sets]
+    opts = R.default_opts(transfer_prec=R.F32)
+    nu = [S.NU_230]
+    before = [ctx.trace_batch(cams, grids, nu, opts) for _ in range(3)]
+    ms_default = min(b[2].kernel_ms for b in before)
+    best, best_ms = R.autotune_batch(ctx, cams, grids, nu, opts, reps=2)
+    got = R.get_plan(ctx, 1, R.F32)
+    assert got.as_dict() == best.as_dict()
+    after = [ctx.trace_batch(cams, grids, nu, opts) for _ in range(3)]
+    ms_tuned = min(a[2].kernel_ms for a in after)
+    print(f"[autotune] default {ms_default:.3f} ms, tuned plan {best.as_dict()} {best_ms:.3f} ms "
+          f"(re-timed {ms_tuned:.3f} ms)", flush=True)
+    assert best_ms <= ms_default * 1.05
+    assert np.array_equal(after[0][0], before[0][0])
+    for h in hs.values():
+        ctx.release_grid(h)
