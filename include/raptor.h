@@ -215,7 +215,8 @@ typedef struct {
  * 256 threads, as many work-groups as fit, refill at 1 idle lane, 8-pixel tile rows, and the
  * variant with the most waves per SIMD (3, 2, then 1) whose RK4 kernel keeps its registers
  * without spilling to scratch; for the learned closures 512 threads and the 2-waves-per-SIMD
- * variant).  RK2 and Verlet runs use the 2-waves-per-SIMD kernel under any plan. */
+ * variant).  RK2 and Verlet runs take the plan's 2- or 3-waves-per-SIMD kernel (2 when the plan
+ * asks for 1). */
 raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
                               raptor_plan* out);
 /* Install a plan for (n_nu, transfer_prec, closure); RAPTOR_E_INVALID if a field is out of range,

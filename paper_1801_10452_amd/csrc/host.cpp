@@ -618,9 +618,9 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
         delete g;
         return dev_fail(ctx, e, "uploading the grid");
     }
-    // start values of the MKS inverse x2(theta) on uniform theta nodes (Newton on the host)
-    // x2(theta) and dx2/dtheta at 1024 nodes (8 KiB: stays in the first-level caches) for the
-    // cubic Hermite start value of the chart inversion
+    // start values of the MKS inverse on uniform theta nodes (Newton on the host): x2(theta) and
+    // dx2/dtheta at 1024 nodes (8 KiB) for the cubic Hermite start value of the chart inversion,
+    // and sin, cos of 2 pi x2 at the stored node values (16 KiB) for its first iteration
     const int x2n = 1024;
     std::vector<float2> x2h(x2n);
     std::vector<double2> sch(x2n);

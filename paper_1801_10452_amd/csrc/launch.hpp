@@ -15,7 +15,7 @@ hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const 
 hipError_t trace_kernel_attributes(int max_nu, bool fp32, int wpe, bool mlpc, int integ, int* vgprs,
                                    int* spill_bytes, int* max_threads);
 // mlpc: the variant with the learned closure; integ: INTEG_* (the second-order integrators have
-// the 2-waves-per-SIMD variant only)
+// the 2- and 3-waves-per-SIMD variants; a request for 1 takes 2)
 const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = false, int integ = INTEG_RK4);
 // dynamic LDS bytes of a trace-kernel work-group of `threads` lanes (mlpc: plus the staged network)
 // Dynamic LDS bytes of a trace launch; the same (wpe, mlpc, integ) select the instantiation in

@@ -653,8 +653,8 @@ __global__ void reset_kernel(unsigned int* tile_counter, unsigned long long* sta
     if (threadIdx.x < ST_COUNT) stats[threadIdx.x] = 0ull;
 }
 
-// Instantiations: RK4 with every register budget (1, 2 or 3 waves per SIMD) and the learned
-// closure (1 or 2); the second-order integrators with the 2-waves-per-SIMD budget only.
+// Instantiations: RK4 with every register budget (1, 2 or 3 waves per SIMD), the learned
+// closure with 1 or 2, the second-order integrators with 2 or 3.
 }  // namespace
 
 int kernel_wpe(int wpe, bool mlpc, int integ)
