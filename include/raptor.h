@@ -226,8 +226,9 @@ raptor_status raptor_set_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_pr
 /* Autotuner: runs the given batch (arguments as raptor_trace_batch, outputs discarded) under
  * candidate plans by coordinate descent over the plan fields, timing each candidate with HIP
  * events as the fastest of `reps` runs, and installs the fastest plan for (n_nu,
- * opts->transfer_prec, opts->closure).  best and best_ms (the fastest kernel time) may be
- * NULL. */
+ * opts->transfer_prec, opts->closure).  best receives the plan as installed (a work-group size
+ * the kernel variant does not allow is reduced, as raptor_set_plan does); best and best_ms (the
+ * fastest kernel time) may be NULL. */
 raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
                                     const raptor_grid* const* grids, const raptor_opts* opts,
                                     const double* nu_hz, int32_t n_nu, int32_t reps, raptor_plan* best,

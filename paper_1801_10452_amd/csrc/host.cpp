@@ -857,7 +857,7 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     if ((s = resolve_plan(ctx, n_nu, fp32, &fin, o.closure >= RAPTOR_CLOSURE_MLP)) != RAPTOR_OK) return s;
     const bool mlpc_t = o.closure >= RAPTOR_CLOSURE_MLP;
     ctx->plans[plan_key(n_nu, fp32, mlpc_t)] = fin;
-    if (best) *best = bp;
+    if (best) *best = fin.p;   // as installed: resolved against the instantiation's limits
     if (best_ms) *best_ms = bms;
     return RAPTOR_OK;
 }
