@@ -104,8 +104,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 4}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
-                                   "in DESIGN.md but not launched"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only: the library shards nothing across GPUs"}))
         sys.exit(2)
 
     import numpy as np
