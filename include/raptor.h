@@ -42,7 +42,7 @@ typedef enum {
     RAPTOR_E_INVALID = -1,      /* bad argument; nothing written */
     RAPTOR_E_NOMEM = -2,        /* device allocation failed */
     RAPTOR_E_DEVICE = -3,       /* HIP runtime error; outputs undefined */
-    RAPTOR_E_UNSUPPORTED = -4,  /* valid but not supported in this build */
+    RAPTOR_E_UNSUPPORTED = -4,  /* valid but not supported by the library */
     RAPTOR_E_RANGE = -5         /* size limit exceeded */
 } raptor_status;
 

@@ -207,14 +207,14 @@ raptor_status raptor_mlp_set_weights(raptor_ctx* ctx, const void* blob, size_t n
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
     const size_t need = sizeof(BlobHeader) + (size_t)3 * NP * sizeof(float);
-    if (!blob || n != need) return fail(ctx, RAPTOR_E_INVALID, "blob size does not match this build's network");
+    if (!blob || n != need) return fail(ctx, RAPTOR_E_INVALID, "blob size does not match the library's network");
     BlobHeader h;
     std::memcpy(&h, blob, sizeof h);
     if (std::memcmp(h.magic, "RAPTMLP", 8) != 0 || h.version != 1 || h.n_params != (uint32_t)NP)
         return fail(ctx, RAPTOR_E_INVALID, "not a version-1 checkpoint of this network");
     if (h.lx_lo != mlp::LX_LO || h.lx_hi != mlp::LX_HI || h.lt_lo != mlp::LT_LO || h.lt_hi != mlp::LT_HI ||
         h.mu_j != mlp::MU_J || h.sigma_j != mlp::SIGMA_J || h.mu_a != mlp::MU_A || h.sigma_a != mlp::SIGMA_A)
-        return fail(ctx, RAPTOR_E_INVALID, "checkpoint normalisation differs from this build's");
+        return fail(ctx, RAPTOR_E_INVALID, "checkpoint normalisation differs from the library's");
     const float* f = (const float*)((const unsigned char*)blob + sizeof h);
     for (int i = 0; i < NP; ++i)
         if (!std::isfinite(f[i])) return fail(ctx, RAPTOR_E_INVALID, "checkpoint holds non-finite parameters");
