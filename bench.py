@@ -80,6 +80,31 @@ def time_form(ctx, R, cams, grids, nu, opts, images, flux, steps, warmup):
             "flux": flux.detach().cpu().numpy().ravel().copy()}
 
 
+def spectrum_slow_light(args):
+    """The slow-light spectrum: 256^2 pixels, 24 frequencies, 64 modulated float32 snapshots;
+    prints one JSON line (kernel time, ray-steps/s and the grid bytes the samples gather)."""
+    import torch
+    import synthetic as S
+    from paper_1801_10452_amd import raptor as R
+    cam, grid, nu = S.slow_light_set()
+    ctx = R.Context(0, use_torch_stream=True)
+    gh = ctx.upload_grid(grid)
+    opts = R.default_opts(transfer_prec=R.F32, slow_light=1)
+    for _ in range(args.warmup):
+        ctx.trace_spectrum(cam, gh, nu, opts)
+    ms, st = [], None
+    for _ in range(args.steps):
+        _, _, st = ctx.trace_spectrum(cam, gh, nu, opts)
+        ms.append(st.kernel_ms)
+    k = sum(ms) / len(ms)
+    # two snapshots x four cells x 16 bytes per sample
+    gather = st.samples * 2 * 4 * 16
+    print(json.dumps({"workload": "spectrum 256x256, 24 frequencies, slow light (64 float32 256^2 snapshots)",
+                      "kernel_ms": k, "ray_steps": st.ray_steps, "samples": st.samples,
+                      "ray_steps_per_s": st.ray_steps / k * 1e3, "gather_bytes_per_launch": gather,
+                      "gather_GBps": gather / k * 1e-6, "grid_bytes": int(grid.cells.nbytes)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +118,9 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "trace_kernel_traffic.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 3 times (HBM counter calibration)")
+    ap.add_argument("--spectrum-slow-light", action="store_true",
+                    help="only time the 256^2 x 24-frequency slow-light spectrum (64 snapshots, 64 MiB of grids): "
+                         "the workload whose grid gathers can reach HBM, for the memory counters")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -106,6 +134,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only: the library shards nothing across GPUs"}))
         sys.exit(2)
+    if args.spectrum_slow_light:
+        spectrum_slow_light(args)
+        return
 
     import numpy as np
     import torch
