@@ -187,3 +187,35 @@ def test_tau_cutoff_full_size(R, ctx, orc, slow_set, nu_set):
     print(f"[tau cutoff {nu_set}] sampled worst rel err {worst:.3e}", flush=True)
     assert worst <= TOL
     ctx.release_grid(gh)
+
+
+def test_light_curve_full_size(R, ctx, orc, slow_set):
+    """A light curve of 32 slow-light frames of the 256^2 camera (t_frame stepping 10 M through
+    the 64-snapshot stack) at the 4 VLBI frequencies, traced as one batch: throughput, frames
+    equal to their single calls, and sampled pixels of two frames against the oracle."""
+    cam0, grid, _ = slow_set
+    gh = ctx.upload_grid(grid)
+    frames = [S.Camera(spin=cam0.spin, incl_deg=cam0.incl_deg, nx=256, ny=256, t_frame=grid.t0 + 160.0 + 10.0 * k)
+              for k in range(32)]
+    nu = S.NU_VLBI
+    opts = R.default_opts(transfer_prec=R.F32, slow_light=1)
+    ctx.trace_batch(frames, [gh] * len(frames), nu, opts)   # warm-up
+    imgs, flux, st = ctx.trace_batch(frames, [gh] * len(frames), nu, opts)
+    flux = np.asarray(flux)
+    print(f"[light curve 32 x 256^2] kernel_ms {st.kernel_ms:.2f}, {st.ray_steps / st.kernel_ms * 1e3:.3e} ray-steps/s, "
+          f"{32 / st.kernel_ms * 1e3:.0f} frames/s; 230 GHz flux min/max "
+          f"{flux[:, 3].min():.4e}/{flux[:, 3].max():.4e} Jy", flush=True)
+    assert st.n_numeric == 0 and np.isfinite(flux).all()
+    assert flux[:, 3].max() > flux[:, 3].min()          # the modulation makes the curve vary
+    for k in (5, 26):
+        _, one, _ = ctx.trace_spectrum(frames[k], gh, nu, opts)
+        assert np.array_equal(np.asarray(one), flux[k])
+    from paper_1801_10452_amd.raptor import split_batch_images
+    parts = split_batch_images(imgs, frames, len(nu))
+    worst = 0.0
+    for k in (9, 22):
+        pix = sample_pixels(frames[k], 8, seed=S.S0 + 970 + k)
+        worst = max(worst, sampled_errors(orc, frames[k], grid, opts, nu, parts[k], pix))
+    print(f"[light curve 32 x 256^2] sampled worst rel err {worst:.3e}", flush=True)
+    assert worst <= TOL
+    ctx.release_grid(gh)
