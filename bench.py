@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "trace_kernel_traffic.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 3 times (HBM counter calibration)")
+    ap.add_argument("--mlp-epochs", type=int, default=0,
+                    help="training epochs of the network (0: the library default); fewer only for profiling the "
+                         "learned-closure kernel, whose cost does not depend on the weights")
     ap.add_argument("--spectrum-slow-light", action="store_true",
                     help="only time the 256^2 x 24-frequency slow-light spectrum (64 snapshots, 64 MiB of grids): "
                          "the workload whose grid gathers can reach HBM, for the memory counters")
@@ -203,7 +206,10 @@ def main():
     }
     if not args.no_mlp:
         R.mlp_init(ctx)
-        rep = R.mlp_train(ctx)
+        cfg = R.mlp_default_cfg()
+        if args.mlp_epochs > 0:
+            cfg.epochs = args.mlp_epochs
+        rep = R.mlp_train(ctx, cfg)
         mlp = time_form(ctx, R, cams, grids, nu,
                         R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=launch, closure=R.CLOSURE_MLP),
                         images, flux, args.steps, args.warmup)
