@@ -183,9 +183,11 @@ struct GlobalWeights {
 // unchanged and no data moves between lanes.
 //
 // LDS layout (bytes): layer 1, four 16x16x16 A fragments, lane l at f * 1024 + l * 16 as
-// {hi[4], lo[4]}; then 26 K = 32 fragments of 2048 bytes, lane l at +l * 32 as {hi[8], lo[8]}:
-// hidden layers 2..4 (index 8 (L - 1) + 2 mt + kq) and the output layer (index 24 + kq); then
-// the hidden biases [4][64] and the two output biases.
+// {hi[4], lo[4]}; then 26 K = 32 fragments of 2048 bytes, each a plane of hi[8] (lane l at
+// +l * 16) followed by a plane of lo[8] (lane l at +1024 + l * 16), so that every fragment read
+// is a run of consecutive 16-byte lane accesses: hidden layers 2..4 (index 8 (L - 1) + 2 mt +
+// kq) and the output layer (index 24 + kq); then the hidden biases [4][64] and the two output
+// biases.
 constexpr int LDS_L1_BYTES = 4 * 64 * 16;
 constexpr int LDS_K32_BYTES = 64 * 32;
 constexpr int LDS_FRAG_BYTES = LDS_L1_BYTES + 26 * LDS_K32_BYTES;
@@ -248,10 +250,11 @@ __device__ inline void stage_weights(const Net& net, unsigned char* lds, int tid
             kq = idx - 24;
         }
         const int ka = 32 * kq, kb = 32 * kq + 16;   // frag_a adds 4 (l / 16)
-        k32[4 * s] = frag_a(net.W + pw, 64, m0, ka, lane);
-        k32[4 * s + 1] = frag_a(net.W + pw, 64, m0, kb, lane);
-        k32[4 * s + 2] = frag_a(net.Wlo + pw, 64, m0, ka, lane);
-        k32[4 * s + 3] = frag_a(net.Wlo + pw, 64, m0, kb, lane);
+        bf16x4* f = k32 + 256 * idx;   // hi plane, then lo plane
+        f[2 * lane] = frag_a(net.W + pw, 64, m0, ka, lane);
+        f[2 * lane + 1] = frag_a(net.W + pw, 64, m0, kb, lane);
+        f[128 + 2 * lane] = frag_a(net.Wlo + pw, 64, m0, ka, lane);
+        f[128 + 2 * lane + 1] = frag_a(net.Wlo + pw, 64, m0, kb, lane);
     }
     float* b = reinterpret_cast<float*>(lds + LDS_FRAG_BYTES);
     for (int i = tid; i < 4 * 64 + 4; i += nthreads)
@@ -271,10 +274,10 @@ __device__ inline Split lds_w1(const unsigned char* lds, int f, int lane)
 template <bool SPLIT>
 __device__ inline Split8 lds_w32(const unsigned char* lds, int idx, int lane)
 {
-    const bf16x8* p = reinterpret_cast<const bf16x8*>(lds + LDS_L1_BYTES + idx * LDS_K32_BYTES + lane * 32);
+    const bf16x8* p = reinterpret_cast<const bf16x8*>(lds + LDS_L1_BYTES + idx * LDS_K32_BYTES);
     Split8 s;
-    s.hi = p[0];
-    s.lo = SPLIT ? p[1] : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    s.hi = p[lane];
+    s.lo = SPLIT ? p[64 + lane] : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
     return s;
 }
 
@@ -307,6 +310,57 @@ __device__ inline f32x4 forward_block_lds(const unsigned char* lds, const Split&
     o.x += bias[256];
     o.y += bias[257];
     return o;
+}
+
+// Two 16-sample column blocks with one read of each weight fragment: half the LDS traffic of two
+// forward_block_lds calls and two independent MFMA / activation chains for the scheduler to
+// interleave.  Each block's arithmetic (operations and their order) is that of
+// forward_block_lds, so the outputs are the same bit for bit.
+template <bool SPLIT>
+__device__ inline void forward_pair_lds(const unsigned char* lds, const Split& bx0, const Split& bx1, int lane,
+                                        f32x4* o0, f32x4* o1)
+{
+    const float* bias = reinterpret_cast<const float*>(lds + LDS_FRAG_BYTES);
+    const int g4 = 4 * (lane >> 4);
+    Split h0[4], h1[4];
+    f32x4 a0[4], a1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const Split w = lds_w1<SPLIT>(lds, mt, lane);
+        a0[mt] = mfma_s<SPLIT>(w, bx0, f32x4{0, 0, 0, 0});
+        a1[mt] = mfma_s<SPLIT>(w, bx1, f32x4{0, 0, 0, 0});
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        h0[mt] = activate<SPLIT>(a0[mt], bias + 16 * mt + g4);
+        h1[mt] = activate<SPLIT>(a1[mt], bias + 16 * mt + g4);
+    }
+#pragma unroll
+    for (int L = 1; L < 4; ++L) {
+        const Split8 p00 = join(h0[0], h0[1]), p01 = join(h0[2], h0[3]);
+        const Split8 p10 = join(h1[0], h1[1]), p11 = join(h1[2], h1[3]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const Split8 w0 = lds_w32<SPLIT>(lds, 8 * (L - 1) + 2 * mt, lane);
+            const Split8 w1 = lds_w32<SPLIT>(lds, 8 * (L - 1) + 2 * mt + 1, lane);
+            a0[mt] = mfma32_s<SPLIT>(w1, p01, mfma32_s<SPLIT>(w0, p00, f32x4{0, 0, 0, 0}));
+            a1[mt] = mfma32_s<SPLIT>(w1, p11, mfma32_s<SPLIT>(w0, p10, f32x4{0, 0, 0, 0}));
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            h0[mt] = activate<SPLIT>(a0[mt], bias + 64 * L + 16 * mt + g4);
+            h1[mt] = activate<SPLIT>(a1[mt], bias + 64 * L + 16 * mt + g4);
+        }
+    }
+    const Split8 w0 = lds_w32<SPLIT>(lds, 24, lane), w1 = lds_w32<SPLIT>(lds, 25, lane);
+    f32x4 r0 = mfma32_s<SPLIT>(w1, join(h0[2], h0[3]), mfma32_s<SPLIT>(w0, join(h0[0], h0[1]), f32x4{0, 0, 0, 0}));
+    f32x4 r1 = mfma32_s<SPLIT>(w1, join(h1[2], h1[3]), mfma32_s<SPLIT>(w0, join(h1[0], h1[1]), f32x4{0, 0, 0, 0}));
+    r0.x += bias[256];
+    r0.y += bias[257];
+    r1.x += bias[256];
+    r1.y += bias[257];
+    *o0 = r0;
+    *o1 = r1;
 }
 
 // Forward pass of one 16-sample column block.  bx: input B fragment (lanes 0..15 hold the
@@ -373,8 +427,8 @@ __device__ inline Split input_block(float x0, float x1, float x2, int cb, int la
 
 // Forward pass for the lanes with active set (all 64 lanes of the wave must call it together):
 // the active lanes' inputs are first packed to lanes 0..n-1 (a permutation through ds_permute),
-// only ceil(n / 16) column blocks are evaluated, and each active lane gets its own outputs
-// back.  Inactive lanes get zeros.
+// only ceil(n / 16) column blocks are evaluated (two at a time while two remain), and each
+// active lane gets its own outputs back.  Inactive lanes get zeros.
 template <bool SPLIT>
 __device__ inline void forward_wave_lds(const unsigned char* lds, bool active, float x0, float x1, float x2, float* y0,
                                         float* y1)
@@ -395,16 +449,32 @@ __device__ inline void forward_wave_lds(const unsigned char* lds, bool active, f
     float r0 = 0.0f, r1 = 0.0f;
     const int ncb = (n + 15) >> 4;
 #pragma unroll 1
-    for (int cb = 0; cb < ncb; ++cb) {
+    for (int cb = 0; cb < ncb; cb += 2) {
         // keep the fragment reads inside the loop: hoisting all 56 of them out of it would hold
-        // 224 registers for the whole pass, where re-reading LDS per column block is cheap
+        // 224 registers for the whole pass, where re-reading LDS per block pair is cheap
         __asm__ volatile("" ::: "memory");
-        const Split bx = input_block<SPLIT>(c0, c1, c2, cb, lane);
-        const f32x4 o = forward_block_lds<SPLIT>(lds, bx, lane);
-        const float v0 = __shfl(o.x, lane & 15, 64), v1 = __shfl(o.y, lane & 15, 64);
-        if ((lane >> 4) == cb) {
-            r0 = v0;
-            r1 = v1;
+        if (cb + 1 < ncb) {
+            const Split bx0 = input_block<SPLIT>(c0, c1, c2, cb, lane), bx1 = input_block<SPLIT>(c0, c1, c2, cb + 1, lane);
+            f32x4 o0, o1;
+            forward_pair_lds<SPLIT>(lds, bx0, bx1, lane, &o0, &o1);
+            const float v0 = __shfl(o0.x, lane & 15, 64), v1 = __shfl(o0.y, lane & 15, 64);
+            const float u0 = __shfl(o1.x, lane & 15, 64), u1 = __shfl(o1.y, lane & 15, 64);
+            if ((lane >> 4) == cb) {
+                r0 = v0;
+                r1 = v1;
+            }
+            if ((lane >> 4) == cb + 1) {
+                r0 = u0;
+                r1 = u1;
+            }
+        } else {
+            const Split bx = input_block<SPLIT>(c0, c1, c2, cb, lane);
+            const f32x4 o = forward_block_lds<SPLIT>(lds, bx, lane);
+            const float v0 = __shfl(o.x, lane & 15, 64), v1 = __shfl(o.y, lane & 15, 64);
+            if ((lane >> 4) == cb) {
+                r0 = v0;
+                r1 = v1;
+            }
         }
     }
     // lane j < n holds the outputs of the j-th active lane

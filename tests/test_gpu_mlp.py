@@ -49,6 +49,22 @@ def test_forward_matches_oracle(R, ctx, orc):
         assert err <= tol
 
 
+def test_forward_independent_of_block_placement(R, ctx, orc):
+    """The LDS-staged forward evaluates a wave's samples in 16-sample column blocks, two blocks
+    per weight read while two remain and a single block for an odd one.  A sample's outputs must
+    not depend on where it lands: the same bits whatever the order of the batch or its length
+    (1000 = 15 full waves + 40 lanes: pairs and one single block; 17: a pair with one sample in
+    its second block; 16 and 5: one single block)."""
+    R.mlp_set_params(ctx, random_params(orc, 7, 0.15))
+    x = np.random.default_rng(8).uniform(-1, 1, (1000, 3)).astype(np.float32)
+    perm = np.random.default_rng(9).permutation(len(x))
+    for form in (R.MLP_SPLIT, R.MLP_BF16):
+        y = R.mlp_forward(ctx, x, form)
+        assert np.array_equal(R.mlp_forward(ctx, x[perm], form), y[perm])
+        for n in (17, 16, 5):
+            assert np.array_equal(R.mlp_forward(ctx, x[:n], form), y[:n])
+
+
 def test_backward_matches_oracle(R, ctx, orc):
     P = random_params(orc, 3, 0.15)
     R.mlp_set_params(ctx, P)
