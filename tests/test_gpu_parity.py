@@ -70,6 +70,25 @@ def test_ragged_and_tiny_images(R, ctx, orc, nx, ny):
     assert np.allclose(flux, ref_flux, rtol=TOL_FP64, atol=0)   # a sum of pixels each within 1e-6
 
 
+@pytest.mark.parametrize("spin,incl", [(-0.9, 60.0), (0.998, 85.0), (0.5, 2.0), (0.9375, 178.0), (0.0, 90.0)])
+def test_extreme_spins_and_inclinations(R, ctx, orc, spin, incl):
+    """Retrograde, near-extremal (horizon at r = 1.063) and zero spin; cameras 2 degrees from
+    either pole, whose rays pass close to the axis where the polar term of the step rule
+    shortens the steps, and edge-on.  20 x 20 over +-15 M of a float64 48 x 40 grid made with
+    the same spin: identical termination codes and step counts, pixels and flux within 1e-6."""
+    g = S.make_grid(48, 40, a_gen=spin, dtype=np.float64)
+    cam = S.Camera(spin=spin, incl_deg=incl, nx=20, ny=20, fov_half=15.0)
+    img, flux, st, status, steps, ref, ref_flux, ref_st = gpu_and_oracle(R, ctx, orc, cam, g, [230e9])
+    print(f"[extreme a={spin} i={incl}] horizon {st.n_horizon} escaped {st.n_escaped} pole {st.n_pole} "
+          f"steps {st.ray_steps}", flush=True)
+    assert (status.ravel() == ref_st[:, 0]).all() and (steps.ravel() == ref_st[:, 1]).all()
+    assert st.n_horizon == (ref_st[:, 0] == R.RAY_HORIZON).sum() and st.n_escaped == (ref_st[:, 0] == R.RAY_ESCAPED).sum()
+    err = rel_err(img, ref)
+    report(f"extreme a={spin} i={incl}", err)
+    assert err.max() <= TOL_FP64
+    assert np.allclose(flux, ref_flux, rtol=TOL_FP64, atol=0)
+
+
 def test_step_limit_writes_zero_and_counts(R, ctx, orc):
     cam, g, nu = S.small_image()
     cam = S.Camera(spin=cam.spin, incl_deg=cam.incl_deg, nx=16, ny=16)
