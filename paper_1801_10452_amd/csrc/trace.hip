@@ -230,6 +230,38 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
     return zamo;
 }
 
+// The learned closure's step contribution in FP32 transfer, by the scheme of Transfer<float>: the
+// network gives ln j_hat + X^1/3 and ln alpha_hat + X^1/3 (standardised); the cut-off factor
+// exp(-X^1/3), common to j and alpha, is split exactly into 2^-n 2^-f, the float arithmetic
+// carries 2^-f and the power of two is applied in double to the step's optical depth and
+// contribution.  j = n_e nu_c J0 e^(ln j_hat), alpha = n_e J0 / (2 m_e nu_c) e^(ln alpha_hat)
+// B_RJ/B_nu, and the source is their ratio.
+__device__ inline void mlp_contribution_f32(const Transfer<float>& tr, float y0, float y1, double nu_obs, double nuc,
+                                            double& A, double& dtau)
+{
+    const double X = nu_obs * tr.nr_inv_nus;
+    if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
+    const double tt = rt::cbrt_refined(X);
+    const double z = ::fmin(tt * 1.4426950408889634, 1100.0);
+    const double n = __builtin_rint(z);
+    const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
+    const double scale = __builtin_ldexp(1.0, -(int)n);
+    const float ej = __expf(y0 * mlp::SIGMA_J + mlp::MU_J), ea = __expf(y1 * mlp::SIGMA_A + mlp::MU_A);
+    const float nucf = (float)nuc;
+    const float yy = (float)pl::H_OVER_MEC2 * (float)(nu_obs * tr.nr) * tr.inv_the;
+    const float planck = (yy > 1e-4f) ? ::expm1f(yy) * rt::rcpf_nr(yy) : 1.0f + 0.5f * yy;   // B_RJ / B_nu
+    const float jm = tr.ne * nucf * (float)pl::J_PREF * ej * em;                                 // j = jm 2^-n
+    const float am = tr.ne * (float)(pl::J_PREF / (2.0 * pl::ME_CGS)) * rt::rcpf_nr(nucf) * ea * em * planck;
+    const float dtm = am * tr.ds;                                                                // dtau = dtm 2^-n
+    dtau = (double)dtm * scale;
+    if (dtau > 1e-8) {
+        A = (double)(jm * rt::rcpf_nr(am) * -::expm1f(-(float)dtau) * tr.inr3);
+    } else {
+        // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): S dtau = j ds to float precision
+        A = (double)(jm * tr.ds * tr.inr3) * scale;
+    }
+}
+
 // Learned-closure variant of eval_sample for one round: every lane of the wave takes part in the
 // network evaluations (one per frequency); lanes without a sample feed zeros.  Samples whose
 // closure inputs leave the training box use the exact closure.
@@ -275,17 +307,21 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
         A[f] = 0.0;
         dtau[f] = 0.0;
         if (inb) {
-            // the network gives ln j_hat + X^1/3 and ln alpha_hat + X^1/3 (standardised); the
-            // coefficients are formed in double from them (their logs span hundreds)
-            const double sb2 = 1.0 - cb * cb;
-            const double tc = rt::cbrt_refined(nu / ((2.0 / 9.0) * nuc * fl[1] * fl[1] * ::sqrt(sb2)));
-            const double lnj = y0 * mlp::SIGMA_J + mlp::MU_J - tc, lna = y1 * mlp::SIGMA_A + mlp::MU_A - tc;
-            const double ne = fl[0];
-            const double j = ne * nuc * pl::J_PREF * ::exp(lnj);
-            const double yy = pl::H_OVER_MEC2 * nu / fl[1];
-            const double planck = (yy > 1e-4) ? ::expm1(yy) / yy : 1.0 + 0.5 * yy;   // B_RJ / B_nu
-            const double al = ne * pl::J_PREF / (2.0 * pl::ME_CGS * nuc) * ::exp(lna) * planck;
-            pl::step_source(j, al, j / al, ds, inr3, A[f], dtau[f]);
+            if constexpr (std::is_same<TT, float>::value) {
+                mlp_contribution_f32(tr, y0, y1, p.nu[li.nu_base + f], nuc, A[f], dtau[f]);
+            } else {
+                // the network gives ln j_hat + X^1/3 and ln alpha_hat + X^1/3 (standardised); the
+                // coefficients are formed in double from them (their logs span hundreds)
+                const double sb2 = 1.0 - cb * cb;
+                const double tc = rt::cbrt_refined(nu / ((2.0 / 9.0) * nuc * fl[1] * fl[1] * ::sqrt(sb2)));
+                const double lnj = y0 * mlp::SIGMA_J + mlp::MU_J - tc, lna = y1 * mlp::SIGMA_A + mlp::MU_A - tc;
+                const double ne = fl[0];
+                const double j = ne * nuc * pl::J_PREF * ::exp(lnj);
+                const double yy = pl::H_OVER_MEC2 * nu / fl[1];
+                const double planck = (yy > 1e-4) ? ::expm1(yy) / yy : 1.0 + 0.5 * yy;   // B_RJ / B_nu
+                const double al = ne * pl::J_PREF / (2.0 * pl::ME_CGS * nuc) * ::exp(lna) * planck;
+                pl::step_source(j, al, j / al, ds, inr3, A[f], dtau[f]);
+            }
         } else if (tr.emits) {
             tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
         }
