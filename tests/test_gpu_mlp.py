@@ -139,6 +139,28 @@ def test_mlp_closure_in_trace_kernel(R, ctx):
     ctx.release_grid(gh)
 
 
+def test_mlp_closure_fp32_transfer_matches_fp64(R, ctx):
+    """With FP32 transfer the learned closure's coefficients are float mantissas whose cut-off
+    factor exp(-X^1/3) keeps its power of two in double; with FP64 transfer they are formed in
+    double from the same network outputs.  Same in-box decisions, and images within the FP32
+    transfer bound (1e-6 per pixel) of each other."""
+    from tests.gpu_common import rel_err
+    if not R.mlp_get_params(ctx).any():
+        R.mlp_init(ctx)
+    cam, g, nu = S.small_image()
+    gh = ctx.upload_grid(g)
+    for cl in (R.CLOSURE_MLP, R.CLOSURE_MLP_BF16):
+        i32, f32, s32 = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32, closure=cl))
+        i64, f64, s64 = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F64, closure=cl))
+        err = rel_err(i32, i64)
+        print(f"[mlp f32 vs f64 closure={cl}] max {err.max():.3e} median {np.median(err):.3e} "
+              f"flux {f32[0] / f64[0] - 1:+.3e} fallback {s32.n_mlp_fallback}/{s32.samples}", flush=True)
+        assert s32.n_mlp_fallback == s64.n_mlp_fallback and s32.samples == s64.samples
+        assert err.max() <= 1e-6
+        assert abs(f32[0] / f64[0] - 1) <= 1e-6
+    ctx.release_grid(gh)
+
+
 def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
     """The learned closure trained with the default configuration (1e7 samples) inside the
     production render (9 images of 512^2, FP64 geodesics, FP32 transfer): total flux within
