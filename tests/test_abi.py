@@ -91,3 +91,20 @@ def test_work_per_step_of_each_integrator():
     assert rk4[0] == pytest.approx(4 * per_eval, rel=0.25)
     with pytest.raises(R.RaptorError):
         R.work_per_step(7)
+
+
+def test_readme_c_example_compiles_and_links(tmp_path):
+    """The C example of the README compiles against the header with every warning as an error,
+    and links against the built library (no GPU is touched: it is not run)."""
+    import subprocess
+    from paper_1801_10452_amd import raptor as R
+    with open(os.path.join(ROOT, "README.md")) as f:
+        blocks = re.findall(r"```c\n(.*?)```", f.read(), flags=re.S)
+    assert len(blocks) == 1
+    src = tmp_path / "app.c"
+    src.write_text(blocks[0])
+    lib_dir = os.path.dirname(R.LIB_PATH) if hasattr(R, "LIB_PATH") else os.path.join(ROOT, "paper_1801_10452_amd")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", str(src), "-I" + os.path.join(ROOT, "include"),
+           "-L" + lib_dir, "-lraptor_hip", "-Wl,--unresolved-symbols=ignore-in-shared-libs", "-o", str(tmp_path / "app")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
