@@ -9,11 +9,14 @@ LIB = os.path.join(HERE, "libraptor_oracle.so")
 
 
 def build(verbose=False):
-    cmd = ["gcc", "-std=gnu99", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
+    # a temporary name of this process's own, so that concurrent builds (parallel test workers)
+    # each replace the library atomically
+    tmp = f"{LIB}.tmp{os.getpid()}"
+    cmd = ["gcc", "-std=gnu99", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libraptor_oracle.so")
 
 EXACT, K2_PAPER, CONST = 0, 1, 2
+MAX_NU = 64   # frequencies per ray the oracle accepts
 RK4, RK2, VERLET, VERLET_CORR = 0, 1, 2, 3
 RUNNING, HORIZON, ESCAPED, MAXSTEP, NUMERIC, OPAQUE, DISK, PLANE = 0, 1, 2, 3, 4, 5, 6, 7
 
@@ -93,14 +94,20 @@ def lib():
         L.orc_fluid_frame.restype = C.c_int
         L.orc_bessel_k2.argtypes = [C.c_double]
         L.orc_bessel_k2.restype = C.c_double
+        L.orc_bessel_k2_scaled.argtypes = [C.c_double]
+        L.orc_bessel_k2_scaled.restype = C.c_double
+        L.orc_ln_bessel_k2.argtypes = [C.c_double]
+        L.orc_ln_bessel_k2.restype = C.c_double
         L.orc_closure.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_double, DP, DP]
         L.orc_planck.argtypes = [C.c_double, C.c_double]
         L.orc_planck.restype = C.c_double
         L.orc_trace_ray.argtypes = [C.POINTER(Camera), C.POINTER(Grid), C.POINTER(Opts), C.c_double,
                                     C.c_double, DP, C.c_int, DP, C.POINTER(RayInfo), C.POINTER(StepRec), C.c_int]
+        L.orc_trace_ray.restype = C.c_int
         L.orc_trace_pixels.argtypes = [C.POINTER(Camera), C.POINTER(Grid), C.POINTER(Opts), DP, C.c_int,
                                        C.POINTER(C.c_int64), C.c_int64, DP, C.POINTER(RayInfo), C.c_int]
+        L.orc_trace_pixels.restype = C.c_int
         L.orc_pixel_solid_angle.argtypes = [C.POINTER(Camera), C.POINTER(Opts)]
         L.orc_pixel_solid_angle.restype = C.c_double
         L.orc_forward_transfer.argtypes = [C.POINTER(StepRec), C.c_int]
@@ -284,6 +291,15 @@ def bessel_k2(x):
     return lib().orc_bessel_k2(x)
 
 
+def bessel_k2_scaled(x):
+    """e^x K_2(x)."""
+    return lib().orc_bessel_k2_scaled(x)
+
+
+def ln_bessel_k2(x):
+    return lib().orc_ln_bessel_k2(x)
+
+
 def planck(nu, thetae):
     return lib().orc_planck(nu, thetae)
 
@@ -304,8 +320,10 @@ def trace_ray(cam, grid_handle, opts, alpha, beta, nu, record=0):
     info = RayInfo()
     c = make_camera(cam)
     rec = (StepRec * record)() if record else None
-    lib().orc_trace_ray(C.byref(c), C.byref(grid_handle.s), C.byref(opts), alpha, beta, _dp(nu), nu.size,
-                        _dp(Iv), C.byref(info), rec, record)
+    rc = lib().orc_trace_ray(C.byref(c), C.byref(grid_handle.s), C.byref(opts), alpha, beta, _dp(nu), nu.size,
+                             _dp(Iv), C.byref(info), rec, record)
+    if rc != 0:
+        raise ValueError(f"oracle: n_nu = {nu.size} outside [1, {MAX_NU}]")
     return Iv, info, rec
 
 
@@ -316,8 +334,10 @@ def trace_pixels(cam, grid_handle, opts, nu, pix, n_threads=0):
     Iv = np.zeros((pix.size, nu.size))
     info = (RayInfo * max(pix.size, 1))()
     c = make_camera(cam)
-    lib().orc_trace_pixels(C.byref(c), C.byref(grid_handle.s), C.byref(opts), _dp(nu), nu.size,
-                           pix.ctypes.data_as(C.POINTER(C.c_int64)), pix.size, _dp(Iv), info, n_threads)
+    rc = lib().orc_trace_pixels(C.byref(c), C.byref(grid_handle.s), C.byref(opts), _dp(nu), nu.size,
+                                pix.ctypes.data_as(C.POINTER(C.c_int64)), pix.size, _dp(Iv), info, n_threads)
+    if rc != 0:
+        raise ValueError(f"oracle: n_nu = {nu.size} outside [1, {MAX_NU}]")
     arr = np.ctypeslib.as_array(info)[: pix.size]
     st = np.array([(r[0], r[1], r[2], r[3]) for r in arr], dtype=np.int64).reshape(-1, 4)
     return Iv, st

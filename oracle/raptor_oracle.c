@@ -665,21 +665,30 @@ int orc_fluid_frame(double a, double M, const double x[4], const double k[4], do
 }
 
 /* Modified Bessel function K_2(x) from its integral representation
- * K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt, trapezoid rule with step 1/32 (the error
- * of the trapezoid rule for this entire, doubly-exponentially decaying integrand is far
- * below double rounding). */
-double orc_bessel_k2(double x)
+ * K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt, evaluated in the scaled form
+ * e^x K_2(x) = int_0^inf exp(-x (cosh t - 1)) cosh(2 t) dt so that cold plasma (large x, where
+ * K_2 itself leaves the double range near x = 700) keeps its value.  Trapezoid rule with step
+ * h = 1/32, shrunk like x^-1/2 above x = 100 where the integrand's peak at t = 0 narrows like
+ * x^-1/2: the error of the trapezoid rule for this entire, doubly-exponentially decaying
+ * integrand, about exp(-2 pi^2 / (x h^2)), then stays below exp(-200) for every x. */
+double orc_bessel_k2_scaled(double x)
 {
-    const double h = 1.0 / 32.0;
-    double sum = 0.5 * exp(-x);
-    for (int n = 1; n < 100000; ++n) {
+    double h = 1.0 / 32.0;
+    if (x > 100.0) h /= sqrt(x / 100.0);
+    double sum = 0.5;
+    for (int n = 1; n < 10000000; ++n) {
         double t = n * h;
-        double term = exp(-x * cosh(t)) * cosh(2.0 * t);
+        double term = exp(-x * (cosh(t) - 1.0)) * cosh(2.0 * t);
         sum += term;
         if (term < 1e-20 * sum) break;
     }
     return h * sum;
 }
+
+double orc_bessel_k2(double x) { return exp(-x) * orc_bessel_k2_scaled(x); }
+
+/* ln K_2(x), finite wherever the scaled integral is. */
+double orc_ln_bessel_k2(double x) { return log(orc_bessel_k2_scaled(x)) - x; }
 
 /* Planck function, Sec. 4.2.2: B_nu = (2 h nu^3 / c^2) / (exp(h nu / (m_e c^2 Theta_e)) - 1). */
 double orc_planck(double nu, double thetae)
@@ -701,9 +710,11 @@ void orc_closure(int mode, double nu, double ne, double thetae, double bfield, d
     double nu_c = O_E * bfield / (2.0 * M_PI * O_ME * O_C);
     double nu_s = (2.0 / 9.0) * nu_c * thetae * thetae * sinb;
     double X = nu / nu_s;
-    double k2 = (mode == ORC_CLOSURE_K2_PAPER) ? 2.0 * thetae * thetae : orc_bessel_k2(1.0 / thetae);
+    /* 1/K2 and the cut-off exp(-X^1/3) are applied as one exponential: each alone can leave the
+     * double range for cold plasma (Theta_e below ~0.0014) where their product does not */
+    double ln_k2 = (mode == ORC_CLOSURE_K2_PAPER) ? log(2.0 * thetae * thetae) : orc_ln_bessel_k2(1.0 / thetae);
     double shape = sqrt(X) + pow(2.0, 11.0 / 12.0) * pow(X, 1.0 / 6.0);
-    double jv = sqrt(2.0) * M_PI * O_E * O_E * ne * nu_s / (3.0 * O_C * k2) * shape * shape * exp(-cbrt(X));
+    double jv = sqrt(2.0) * M_PI * O_E * O_E * ne * nu_s / (3.0 * O_C) * shape * shape * exp(-cbrt(X) - ln_k2);
     *j = jv;
     *alpha = jv / orc_planck(nu, thetae);
 }
@@ -725,10 +736,11 @@ double orc_length_unit(double mass_msun) { return O_G * mass_msun * O_MSUN / (O_
  * formal-solution equation), attenuated by the optical depth already between the point and
  * the camera (backward-transfer equation), and converted to observed intensity with the
  * invariant I/nu^3 (Sec. 3.1).  No optical-depth cut-off. */
-void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
-                   double alpha, double beta, const double* nu, int n_nu, double* Iout,
-                   orc_ray_info* info, orc_step_rec* rec, int rec_cap)
+int orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
+                  double alpha, double beta, const double* nu, int n_nu, double* Iout,
+                  orc_ray_info* info, orc_step_rec* rec, int rec_cap)
 {
+    if (n_nu < 1 || n_nu > ORC_MAX_NU) return -1;
     double M = o->metric_mass, a = cam->spin;
     double rh = M + sqrt(M * M - a * a);
     double r_stop = o->r_stop_factor * rh;
@@ -736,7 +748,7 @@ void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* 
     double y[8], yn[8], acc[4];
     int have_acc = 0;
     orc_camera_ray(cam, M, alpha, beta, cam->t_frame + cam->r_cam, y, NULL);
-    double tau[64];
+    double tau[ORC_MAX_NU];
     for (int f = 0; f < n_nu; ++f) { Iout[f] = 0.0; tau[f] = 0.0; }
     int steps = 0, samples = 0, poles = 0, status = ORC_RUNNING;
     while (status == ORC_RUNNING) {
@@ -790,12 +802,14 @@ void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* 
     if (status == ORC_NUMERIC)
         for (int f = 0; f < n_nu; ++f) Iout[f] = 0.0;
     if (info) { info->status = status; info->steps = steps; info->samples = samples; info->poles = poles; }
+    return 0;
 }
 
-void orc_trace_pixels(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
+int orc_trace_pixels(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
                       const double* nu, int n_nu, const int64_t* pix, int64_t n_pix,
                       double* Iout, orc_ray_info* info, int n_threads)
 {
+    if (n_nu < 1 || n_nu > ORC_MAX_NU) return -1;
 #ifdef _OPENMP
     if (n_threads <= 0) n_threads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 4) num_threads(n_threads)
@@ -806,6 +820,7 @@ void orc_trace_pixels(const orc_camera* cam, const orc_grid* grid, const orc_opt
         orc_pixel_alpha_beta(cam, i, j, &al, &be);
         orc_trace_ray(cam, grid, o, al, be, nu, n_nu, Iout + p * n_nu, info ? &info[p] : NULL, NULL, 0);
     }
+    return 0;
 }
 
 /* Solid angle of one pixel seen from distance D: (2F/nx)(2F/ny) L^2 / D^2 (Sec. 4.2.2, flux

@@ -94,6 +94,8 @@ int  orc_grid_sample(const orc_grid* g, int slow_light, double t_frame, double r
 int  orc_fluid_frame(double a, double M, const double x[4], const double k[4], double omega,
                      double u[4], double b[4], double* nu_r, double* cos_b);
 double orc_bessel_k2(double x);
+double orc_bessel_k2_scaled(double x);   /* e^x K_2(x) */
+double orc_ln_bessel_k2(double x);      /* ln K_2(x) */
 void orc_closure(int mode, double nu, double ne, double thetae, double bfield, double cos_b,
                  double const_j, double const_alpha, double* j, double* alpha);
 double orc_planck(double nu, double thetae);
@@ -116,10 +118,13 @@ void orc_disk_profile(const orc_camera* cam, const double* g, const double* Iv, 
                       double g_hi, double* profile);
 
 /* transfer and products ---------------------------------------------------------------- */
-void orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
+/* Frequencies per ray: 1 <= n_nu <= ORC_MAX_NU; the tracing calls return -1 (and write
+ * nothing) outside that range, 0 otherwise. */
+enum { ORC_MAX_NU = 64 };
+int  orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
                    double alpha, double beta, const double* nu, int n_nu, double* I,
                    orc_ray_info* info, orc_step_rec* rec, int rec_cap);
-void orc_trace_pixels(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
+int  orc_trace_pixels(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
                       const double* nu, int n_nu, const int64_t* pix, int64_t n_pix,
                       double* I /* [n_pix][n_nu] */, orc_ray_info* info /* [n_pix] or NULL */,
                       int n_threads);

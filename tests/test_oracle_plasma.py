@@ -126,6 +126,48 @@ def test_bessel_k2_against_scipy(orc, x):
     assert orc.bessel_k2(x) == pytest.approx(special.kn(2, x), rel=1e-13)
 
 
+@pytest.mark.parametrize("x", [1e-4, 0.02, 2.0, 50.0, 150.0, 700.0, 800.0, 3000.0, 1e4, 1e5])
+def test_scaled_bessel_k2_against_scipy(orc, x):
+    """e^x K2(x) over the whole range, including cold plasma (x = 1/Theta_e up to 1e5) where K2
+    itself underflows."""
+    assert orc.bessel_k2_scaled(x) == pytest.approx(special.kve(2, x), rel=1e-13)
+    assert orc.ln_bessel_k2(x) == pytest.approx(math.log(special.kve(2, x)) - x, rel=1e-15, abs=1e-13)
+
+
+@pytest.mark.parametrize("x", [200.0, 1000.0, 3e4])
+def test_ln_k2_large_argument_asymptotic_series(orc, x):
+    """Large-argument expansion (Abramowitz & Stegun 9.7.2):
+    K_nu(x) ~ sqrt(pi/(2x)) e^-x sum_k a_k(nu) / x^k, a_k = prod_{i=1..k} (4 nu^2 - (2i-1)^2) / (k! 8^k)."""
+    mu, term, ser = 16.0, 1.0, 1.0
+    for k in range(1, 12):
+        term *= (mu - (2 * k - 1) ** 2) / (k * 8.0 * x)
+        ser += term
+    want = 0.5 * math.log(math.pi / (2 * x)) - x + math.log(ser)
+    assert orc.ln_bessel_k2(x) == pytest.approx(want, rel=1e-15, abs=1e-12)
+
+
+@pytest.mark.parametrize("th", [0.01, 0.005, 0.001])
+def test_closure_of_cold_plasma_stays_finite(orc, th):
+    """Cold electrons: 1/K2(1/Theta_e) and exp(-X^1/3) are each outside the double range for
+    Theta_e = 0.001 while their product, the emissivity, is not (frequencies chosen so that
+    X^1/3 exceeds 1/Theta_e by 5 to 60).  j matches the same fit with K2 from scipy's scaled
+    Bessel function, and Kirchhoff's law holds."""
+    x = 1.0 / th
+    for ne, B, cb in [(1e6, 300.0, 0.2), (1e5, 1e3, -0.6), (1e6, 30.0, 0.5)]:
+        nuc = E_ESU * B / (2 * math.pi * ME * C)
+        nus = (2.0 / 9.0) * nuc * th * th * math.sqrt(1 - cb * cb)
+        for d in (5.0, 20.0, 60.0):
+            X = (x + d) ** 3
+            nu = X * nus
+            j, a = orc.closure(nu, ne, th, B, cb)
+            assert math.isfinite(j) and math.isfinite(a) and j > 0.0
+            lnj = (math.log(math.sqrt(2) * math.pi * E_ESU ** 2 * ne * nus / (3 * C))
+                   + 2 * math.log(math.sqrt(X) + 2 ** (11 / 12) * X ** (1 / 6)) - X ** (1 / 3) + x
+                   - math.log(special.kve(2, x)))
+            assert j == pytest.approx(math.exp(lnj), rel=1e-11)
+            assert a * orc.planck(nu, th) == pytest.approx(j, rel=1e-13)
+
+
 def test_k2_paper_approximation_limit(orc):
     """K2(1/Theta) / (2 Theta^2) -> 1 for hot electrons, which ties the paper's approximation
     to the exact closure."""
