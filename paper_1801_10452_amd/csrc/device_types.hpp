@@ -38,7 +38,8 @@ struct DevJob {
 // ln K2(1/Theta) on octaves of Theta: Theta = m 2^e with m in [1/2, 1) (frexp), octave
 // e = e_lo + o (o < n_oct) split into nsub intervals uniform in m.  Entry o nsub + j holds
 // {f0, d0, f1, d1}: ln K2 at the interval's two ends and its derivatives with respect to the
-// interval's own coordinate s in [0, 1] (cubic Hermite); Theta is clamped to [th_lo, th_hi].
+// interval's own coordinate s in [0, 1] (cubic Hermite).  Outside [th_lo, th_hi] the lookup
+// takes K2's large- and small-argument expansions instead.
 struct K2Table {
     const double4* tab;
     int e_lo, n_oct, nsub, pad;

@@ -258,12 +258,26 @@ __host__ __device__ inline bool fluid_frame(T a, T a2, T M, const T* y, T s, T c
 }
 
 // ln K2(1/Theta) from the octave table: the binary exponent and mantissa of Theta select the
-// interval (no logarithm), cubic Hermite interpolation inside it.
+// interval (no logarithm), cubic Hermite interpolation inside it.  Outside the table's range
+// the large- and small-argument expansions of K2 are exact to rounding there:
+//   x = 1/Theta > 128:   ln K2 = -x + 1/2 ln(pi / 2x) + ln(1 + sum_k a_k x^-k),
+//                        a_k = prod_{i=1..k} (16 - (2i - 1)^2) / (k! 8^k) (Hankel's series,
+//                        Abramowitz & Stegun 9.7.2; six terms leave < 1e-14 at x = 128);
+//   x = 1/Theta < 2^-14: ln K2 = ln(2 / x^2) - x^2 / 4 (K2 = 2/x^2 - 1/2 + O(x^2 ln x)).
 __host__ __device__ inline double ln_k2_theta(const K2Table& t, double the)
 {
-    const double th = ::fmin(::fmax(the, t.th_lo), t.th_hi);
+    if (the < t.th_lo) {
+        const double x = 1.0 / the, u = the * 0.125;   // u = 1/(8x)
+        // 1 + a_1/x + ... + a_6/x^6 with a_k/x^k = c_k u^k, c_k = prod (16 - (2i-1)^2) / k!
+        double p = 1.0 + u * (15.0 + u * (52.5 + u * (-157.5 + u * (1299.375 + u * (-16891.875 + u * 295607.8125)))));
+        return -x + 0.5 * rt::log_pos(0.5 * PI_D * the) + rt::log_pos(p);
+    }
+    if (the > t.th_hi) {
+        const double x = 1.0 / the;
+        return 0.6931471805599453 + 2.0 * rt::log_pos(the) - 0.25 * x * x;
+    }
     int e;
-    const double m = __builtin_frexp(th, &e);            // th = m 2^e, m in [1/2, 1)
+    const double m = __builtin_frexp(the, &e);           // the = m 2^e, m in [1/2, 1)
     const double q = (m - 0.5) * (double)(2 * t.nsub);   // exact: a power-of-two scaling
     int j = (int)q;
     j = j < t.nsub - 1 ? j : t.nsub - 1;
@@ -278,16 +292,18 @@ __host__ __device__ inline double ln_k2_theta(const K2Table& t, double the)
 // Emission j_nu and absorption alpha_nu in the fluid frame (Sec. 4.2.2): Leung et al. fit
 // with nu_s = (2/9) nu_c Theta_e^2 sin(theta_B), X = nu/nu_s,
 // (X^1/2 + 2^11/12 X^1/6)^2 = X^1/3 (X^1/3 + 2^11/12)^2, and alpha = j / B_nu.  *bnu gets
-// B_nu (the source function j/alpha of thermal emission).  k2_inv = 1 / K2(1/Theta_e).
+// B_nu (the source function j/alpha of thermal emission).  ln_k2 = ln K2(1/Theta_e): 1/K2 and
+// the cut-off exp(-X^1/3) are applied as one exponential, since either alone leaves the double
+// range for cold plasma (Theta_e below ~0.0014) where their product need not.
 template <class T>
-__host__ __device__ inline void closure_exact(T nu, T ne, T the, T bf, T sinb, T k2_inv, T* j, T* alpha, T* bnu)
+__host__ __device__ inline void closure_exact(T nu, T ne, T the, T bf, T sinb, T ln_k2, T* j, T* alpha, T* bnu)
 {
     using namespace rt;
     const T nu_s = T(2.0 / 9.0 * NUC_PER_GAUSS) * bf * the * the * sinb;
     const T X = nu / nu_s;
     const T t = cbrt_(X);
     const T tc = t + T(TWO_11_12);
-    const T jv = T(J_PREF) * ne * nu_s * k2_inv * t * tc * tc * exp_(-t);
+    const T jv = T(J_PREF) * ne * nu_s * t * tc * tc * exp_(-(t + ln_k2));
     const T B = T(PLANCK_PREF) * nu * nu * nu / expm1_(T(H_OVER_MEC2) * nu / the);
     *j = jv;
     *alpha = jv / B;

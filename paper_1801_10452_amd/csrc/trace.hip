@@ -42,7 +42,7 @@ struct Transfer;
 template <>
 struct Transfer<double> {
     // per-sample, frequency-independent part
-    double ne, the, bf, sinb, k2_inv, ds, inr3, nr;
+    double ne, the, bf, sinb, ln_k2, ds, inr3, nr;
     bool emits;
     __device__ inline void setup(const TraceParams& p, const double fl[4], double nr_, double cosb, double dsv)
     {
@@ -53,9 +53,9 @@ struct Transfer<double> {
         const double s2 = 1.0 - cosb * cosb;
         sinb = s2 > 0.0 ? s2 * rt::rsqrt_nr(s2) : 0.0;
         emits = (ne > 0.0 && the > 0.0 && bf > 0.0 && sinb > 0.0);
-        k2_inv = 0.0;
+        ln_k2 = 0.0;
         if (emits && p.closure != CL_CONST)
-            k2_inv = (p.closure == CL_K2_PAPER) ? 1.0 / (2.0 * the * the) : ::exp(-pl::ln_k2_theta(p.k2, the));
+            ln_k2 = (p.closure == CL_K2_PAPER) ? ::log(2.0 * the * the) : pl::ln_k2_theta(p.k2, the);
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
@@ -65,7 +65,7 @@ struct Transfer<double> {
             al = p.const_alpha;
             S = al > 0.0 ? j / al : 0.0;
         } else if (emits) {
-            pl::closure_exact(nu_obs * nr, ne, the, bf, sinb, k2_inv, &j, &al, &S);
+            pl::closure_exact(nu_obs * nr, ne, the, bf, sinb, ln_k2, &j, &al, &S);
         } else {
             return;
         }
@@ -76,13 +76,16 @@ struct Transfer<double> {
 // FP32 transfer.  The coefficients j, alpha, S and the step's contribution are float
 // mantissas; the arguments of the exponentials whose size amplifies rounding -- X^1/3 in the
 // emissivity (up to ~40 where the flux matters) and ln K2 -- are formed in double.  The
-// cut-off factor exp(-X^1/3) is split exactly into 2^-n 2^-f: the float arithmetic carries the
-// mantissa 2^-f and the power of two 2^-n is applied in double at the end, so emission far
-// below the float range (X^1/3 > 87, common at high frequencies) keeps its value instead of
-// flushing to zero.  The results (contribution and optical depth of the step) are doubles.
+// factor 1/K2 exp(-X^1/3) = exp(-(ln K2 + X^1/3)) is split exactly into 2^-n 2^-f: the float
+// arithmetic carries the mantissa 2^-f and the power of two 2^-n is applied in double at the
+// end, so emission far below the float range (X^1/3 > 87, common at high frequencies) keeps its
+// value instead of flushing to zero, and so does the large 1/K2 of cold plasma (Theta_e below
+// ~0.01, where 1/K2 alone exceeds the float range).  The results (contribution and optical
+// depth of the step) are doubles.
 template <>
 struct Transfer<float> {
-    float ne, the, inv_the, nu_s, k2_inv, ds, inr3;
+    float ne, the, inv_the, nu_s, ds, inr3;
+    double ln_k2;        // ln K2(1/Theta_e) (ln 2 Theta_e^2 for the paper's closure)
     double nr_inv_nus;   // nu_r / nu_s: X = nu_obs nu_r / nu_s in double
     double nr;
     bool emits;
@@ -100,10 +103,9 @@ struct Transfer<float> {
         const double nus = (2.0 / 9.0) * pl::NUC_PER_GAUSS * fl[2] * fl[1] * fl[1] * sb;
         nu_s = (float)nus;
         nr_inv_nus = emits ? nr_ * rt::rcp_nr(nus) : 0.0;
-        k2_inv = 0.0f;
+        ln_k2 = 0.0;
         if (emits && p.closure != CL_CONST)
-            k2_inv = (p.closure == CL_K2_PAPER) ? 1.0f / (2.0f * the * the)
-                                               : rt::exp_mixed(-pl::ln_k2_theta(p.k2, fl[1]));
+            ln_k2 = (p.closure == CL_K2_PAPER) ? rt::log_pos(2.0 * fl[1] * fl[1]) : pl::ln_k2_theta(p.k2, fl[1]);
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
@@ -119,14 +121,15 @@ struct Transfer<float> {
         const double X = nu_obs * nr_inv_nus;
         if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
         const double tt = rt::cbrt_refined(X);
-        // exp(-tt) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in double too
-        const double z = ::fmin(tt * 1.4426950408889634, 1100.0);
+        // exp(-(ln K2 + tt)) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in
+        // double too, and the exponent is kept above -1000 so that the scale stays finite
+        const double z = ::fmax(::fmin((tt + ln_k2) * 1.4426950408889634, 1100.0), -1000.0);
         const double n = __builtin_rint(z);
         const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
         const double scale = __builtin_ldexp(1.0, -(int)n);
         const float t = (float)tt;
         const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
-        const float jm = 1.1396857174835936e-29f * ne * nu_s * k2_inv * t * tc * tc * em;   // j = jm 2^-n
+        const float jm = 1.1396857174835936e-29f * ne * nu_s * t * tc * tc * em;   // j = jm 2^-n
         const float nuf = (float)(nu_obs * nr);
         const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
         const float q3 = q * q * q;                               // 2 h nu^3 / c^2

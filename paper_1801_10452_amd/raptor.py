@@ -217,12 +217,32 @@ def work_per_unit():
     return {k: x.value for k, x in zip(keys, v)}
 
 
-def _ptr(a):
-    """Address of a numpy array or torch tensor (None -> NULL)."""
+def _out(a, n, kind, mem, device, name):
+    """Check a caller-supplied output buffer before its address is handed to the library: in
+    host mode a C-contiguous numpy array, in device mode a contiguous torch tensor on the
+    context's device; dtype float64 (kind "f8") or int32 ("i4"); at least n elements.  Raises
+    RaptorError(E_INVALID) on a mismatch.  Returns the address (None for None)."""
     if a is None:
         return None
-    if isinstance(a, np.ndarray):
+    if mem == MEM_HOST:
+        if not isinstance(a, np.ndarray):
+            raise RaptorError(E_INVALID, f"{name}: host mode needs a numpy array, got {type(a).__name__}")
+        if a.dtype != np.dtype(kind) or not a.flags.c_contiguous or not a.flags.writeable:
+            raise RaptorError(E_INVALID, f"{name}: needs a writeable C-contiguous {np.dtype(kind)} array, "
+                                         f"got {a.dtype} (contiguous={a.flags.c_contiguous})")
+        if a.size < n:
+            raise RaptorError(E_INVALID, f"{name}: {a.size} elements, {n} needed")
         return a.ctypes.data
+    import torch
+    if not isinstance(a, torch.Tensor):
+        raise RaptorError(E_INVALID, f"{name}: device mode needs a torch tensor, got {type(a).__name__}")
+    want = torch.float64 if kind == "f8" else torch.int32
+    if a.dtype != want or not a.is_contiguous():
+        raise RaptorError(E_INVALID, f"{name}: needs a contiguous {want} tensor, got {a.dtype}")
+    if not a.is_cuda or (a.device.index if a.device.index is not None else 0) != device:
+        raise RaptorError(E_INVALID, f"{name}: tensor on {a.device}, the context is on cuda:{device}")
+    if a.numel() < n:
+        raise RaptorError(E_INVALID, f"{name}: {a.numel()} elements, {n} needed")
     return a.data_ptr()
 
 
@@ -245,6 +265,7 @@ class Context:
         if st != OK:
             raise RaptorError(st, lib().raptor_last_error(None).decode())
         self.h = h
+        self.device = device
         self._grids = []
 
     def close(self):
@@ -290,9 +311,11 @@ class Context:
                 flux = np.zeros(nu.size)
         st = CStats()
         c = make_camera(cam)
+        npix, m, d = cam.nx * cam.ny, opts.mem, self.device
+        args = (_out(images, nu.size * npix, "f8", m, d, "images"), _out(flux, nu.size, "f8", m, d, "flux"),
+                _out(ray_status, npix, "i4", m, d, "ray_status"), _out(ray_steps, npix, "i4", m, d, "ray_steps"))
         self._check(lib().raptor_trace_spectrum_ex(self.h, C.byref(c), C.c_void_p(grid.ptr), C.byref(opts),
-                                                   nu.ctypes.data_as(DP), nu.size, _ptr(images), _ptr(flux),
-                                                   _ptr(ray_status), _ptr(ray_steps), C.byref(st)))
+                                                   nu.ctypes.data_as(DP), nu.size, *args, C.byref(st)))
         return images, flux, st
 
     def trace_image(self, cam, grid, nu, opts=None, image=None, flux=None):
@@ -304,8 +327,10 @@ class Context:
                 flux = np.zeros(1)
         st = CStats()
         c = make_camera(cam)
+        npix, m, d = cam.nx * cam.ny, opts.mem, self.device
         self._check(lib().raptor_trace_image(self.h, C.byref(c), C.c_void_p(grid.ptr), C.byref(opts), float(nu),
-                                             _ptr(image), _ptr(flux), C.byref(st)))
+                                             _out(image, npix, "f8", m, d, "image"), _out(flux, 1, "f8", m, d, "flux"),
+                                             C.byref(st)))
         return image, flux, st
 
     def trace_disk(self, cam, opts=None, r_disk_out=15.0, n_bins=256, g_lo=0.0, g_hi=2.0, intensity=None,
@@ -322,9 +347,13 @@ class Context:
                 profile = np.zeros(n_bins)
         st = CStats()
         c = make_camera(cam)
+        npix, m, d = cam.nx * cam.ny, opts.mem, self.device
         self._check(lib().raptor_trace_disk(self.h, C.byref(c), C.byref(opts), r_disk_out, n_bins, g_lo, g_hi,
-                                            _ptr(intensity), _ptr(redshift), _ptr(profile), _ptr(ray_status),
-                                            _ptr(ray_steps), C.byref(st)))
+                                            _out(intensity, npix, "f8", m, d, "intensity"),
+                                            _out(redshift, npix, "f8", m, d, "redshift"),
+                                            _out(profile, max(n_bins, 0), "f8", m, d, "profile"),
+                                            _out(ray_status, npix, "i4", m, d, "ray_status"),
+                                            _out(ray_steps, npix, "i4", m, d, "ray_steps"), C.byref(st)))
         return intensity, redshift, profile, st
 
     def trace_batch(self, cams, grids, nu, opts=None, images=None, flux=None):
@@ -346,8 +375,10 @@ class Context:
         carr = (CCamera * n)(*[make_camera(c) for c in cams])
         garr = (C.c_void_p * n)(*[g.ptr for g in grids])
         st = CStats()
+        m, d = opts.mem, self.device
         self._check(lib().raptor_trace_batch(self.h, carr, n, garr, C.byref(opts), nu.ctypes.data_as(DP), n_nu,
-                                             _ptr(images), _ptr(flux), C.byref(st)))
+                                             _out(images, total, "f8", m, d, "images"),
+                                             _out(flux, n * n_nu, "f8", m, d, "flux"), C.byref(st)))
         return images, flux, st
 
 

@@ -7,10 +7,17 @@ import synthetic as S
 
 
 def rel_err(gpu, ref, floor_frac=1e-10):
-    """|I_gpu - I_ref| / max(|I_ref|, floor_frac * max|I_ref|), elementwise."""
+    """|I_gpu - I_ref| / max(|I_ref|, floor_frac * max|I_ref|), elementwise.  For a stack of
+    images ([n_nu][ny][nx], or more leading axes) the floor is taken per image, from that
+    image's own brightest pixel, so that a dim frequency is judged against itself and not
+    against the brightest frequency of the stack."""
     gpu = np.asarray(gpu, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    floor = floor_frac * max(np.abs(ref).max(), 1e-300)
+    if ref.ndim >= 3:
+        peak = np.abs(ref).max(axis=(-2, -1), keepdims=True)
+    else:
+        peak = np.abs(ref).max() if ref.size else 0.0
+    floor = floor_frac * np.maximum(peak, 1e-300)
     return np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
 
 

@@ -324,3 +324,46 @@ def test_tau_cutoff_matches_oracle(R, ctx, orc, prec):
     err = rel_err(img, ref)
     report(f"tau cutoff {prec}", err)
     assert err.max() <= TOL_FP64
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n_nu", [6, 12])
+def test_eight_and_sixteen_frequency_kernels(R, ctx, orc, prec, n_nu):
+    """6 and 12 frequencies select the kernels compiled for up to 8 and 16 frequencies per ray
+    (the spectrum tests use 1-4 and 24).  24 x 20 pixels (ragged 8 x 8 tiles) on a float32 48^2
+    grid, log-spaced 1 GHz to 10 THz: same status and steps per ray as the oracle, every
+    frequency's image within 1e-6 per pixel of its own brightest pixel's floor, fluxes to 1e-6."""
+    g = S.make_grid(48, 48, a_gen=0.9375, dtype=np.float32)
+    cam = S.Camera(spin=0.9375, incl_deg=60.0, nx=24, ny=20, fov_half=15.0)
+    nu = list(np.geomspace(1e9, 1e13, n_nu))
+    img, flux, st, status, steps, ref, ref_flux, ref_st = gpu_and_oracle(
+        R, ctx, orc, cam, g, nu, transfer_prec=R.F64 if prec == "f64" else R.F32)
+    assert (status.ravel() == ref_st[:, 0]).all() and (steps.ravel() == ref_st[:, 1]).all()
+    err = rel_err(img, ref)
+    for f in range(n_nu):
+        report(f"{n_nu} frequencies {prec}, {nu[f]:.3g} Hz", err[f])
+    assert err.max() <= TOL_FP64
+    assert np.allclose(flux, ref_flux, rtol=TOL_FP64, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("scale,nu", [(1e-3, [1e8, 1e9, 1e10]), (3e-3, [1e8, 1e9, 230e9]),
+                                      (3e3, [1e9, 230e9, 1e13])])
+def test_cold_and_hot_plasma(R, ctx, orc, prec, scale, nu):
+    """Electron temperatures beyond the K2 table: the torus with Theta_e scaled by 1e-3 and 3e-3
+    (Theta_e from 4e-4 to 0.05, where 1/K2 alone exceeds the float range and, below ~0.0014, the
+    double range) and by 3e3 (up to 5e4, above the table's 2^14).  The closure applies 1/K2 and the
+    cut-off exp(-X^1/3) as one exponential in both precisions; per pixel and flux within 1e-6 of
+    the oracle, whose K2 is the integral representation (no table)."""
+    g = S.make_grid(40, 40, a_gen=0.5, dtype=np.float64)
+    g.cells[..., 1] *= scale
+    cam = S.Camera(spin=0.5, incl_deg=60.0, nx=24, ny=24, fov_half=15.0)
+    img, flux, st, status, steps, ref, ref_flux, ref_st = gpu_and_oracle(
+        R, ctx, orc, cam, g, nu, transfer_prec=R.F64 if prec == "f64" else R.F32)
+    assert np.isfinite(img).all() and st.n_numeric == 0
+    assert all((ref[f] > 0).any() for f in range(len(nu)))
+    err = rel_err(img, ref)
+    for f in range(len(nu)):
+        report(f"Theta_e x {scale:g} {prec}, {nu[f]:.3g} Hz", err[f])
+    assert err.max() <= TOL_FP64
+    assert np.allclose(flux, ref_flux, rtol=TOL_FP64, atol=0)
