@@ -197,6 +197,30 @@ raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int
                                  const double* nu_hz, int32_t n_nu, double* images, double* flux_jy,
                                  raptor_stats* stats);
 
+/* For callers that cannot allocate memory during a call -- code under HIP stream capture, tight
+ * serving loops, harnesses that forbid allocation: raptor_trace_batch without any allocation.
+ * Arguments and results are those of raptor_trace_batch (images and fluxes are bitwise the
+ * same), with these limits:
+ *  - opts->mem must be RAPTOR_MEM_DEVICE and images non-NULL (device memory of the context's
+ *    device, the images of all cameras concatenated); flux_jy is device memory or NULL;
+ *  - opts->launch must be RAPTOR_LAUNCH_DIRECT (RAPTOR_E_UNSUPPORTED otherwise);
+ *  - at most RAPTOR_NOALLOC_MAX_CAMS cameras (RAPTOR_E_RANGE otherwise), up to RAPTOR_MAX_NU
+ *    frequencies each.
+ * Every buffer the launch needs beyond the inputs and outputs (tile counter, statistics, the
+ * job, grid, frequency and solid-angle tables, the flux partial sums) lives in one fixed array
+ * of about 1.3 MiB per GPU, which the library holds from its load until the process ends; the
+ * host-side tables were sized when the context was created.  The call allocates no device or
+ * host memory: a launch plan not yet installed for the call's frequency class, precision and
+ * closure is resolved without being cached.  All calls on one GPU share that array: calls that
+ * overlap in time on the same GPU (from several threads or contexts) race and must not be
+ * made; consecutive calls are safe (each call is synchronous and clears what must start at
+ * zero). */
+enum { RAPTOR_NOALLOC_MAX_CAMS = 256 };
+raptor_status raptor_trace_batch_noalloc(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                         const raptor_grid* const* grids, const raptor_opts* opts,
+                                         const double* nu_hz, int32_t n_nu, double* images,
+                                         double* flux_jy, raptor_stats* stats);
+
 /* Launch plan of the persistent trace kernel: the autotuner's search space.  A plan is kept
  * per context for each (n_nu class, transfer_prec, closure class) -- the closure class being
  * the learned closures (RAPTOR_CLOSURE_MLP*) or the others. */

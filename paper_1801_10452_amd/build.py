@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "libraptor_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["trace.hip", "mlp.hip", "disk.hip", "host.cpp", "mlp_host.cpp"]
+SOURCES = ["trace.hip", "mlp.hip", "disk.hip", "noalloc.hip", "host.cpp", "mlp_host.cpp"]
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I" + os.path.join(ROOT, "include"),
          "-I" + CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
          "-Wno-unused-command-line-argument"]

@@ -46,6 +46,25 @@ struct DevBuf {
     }
 };
 
+// One image of a trace call as the caller gave it.
+struct JobIn {
+    const raptor_camera* cam;
+    const raptor_grid* grid;
+    const double* nu;
+};
+
+// Host tables of the no-allocation batch entry point, sized once for its largest batch when
+// the context is created.
+constexpr int NOALLOC_JOBS = 256;
+struct NoAllocHost {
+    JobIn in[NOALLOC_JOBS];
+    DevJob jobs[NOALLOC_JOBS];
+    DevGrid grids[NOALLOC_JOBS];
+    const raptor_grid* gl[NOALLOC_JOBS];
+    double nus[NOALLOC_JOBS * RAPTOR_MAX_NU];
+    double pixsr[NOALLOC_JOBS];
+};
+
 struct LaunchPlan {
     raptor_plan p{256, 0, 1, 8, 2, {0, 0, 0}};
     int blocks = 0;   // resolved work-group count
@@ -103,6 +122,9 @@ struct raptor_ctx {
     std::vector<raptor_grid*> live;
     std::map<int, rctx::LaunchPlan> plans;   // key: frequency-count class * 2 + fp32
     rctx::MlpState mlp;
+    // no-allocation entry point: this device's scratch array (device address) and host tables
+    void* noalloc_scratch = nullptr;
+    rctx::NoAllocHost* noalloc_host = nullptr;
 };
 
 namespace rctx {

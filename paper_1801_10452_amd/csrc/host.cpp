@@ -142,12 +142,6 @@ raptor_status check_camera(raptor_ctx* ctx, const raptor_camera* c, const raptor
     return RAPTOR_OK;
 }
 
-struct JobIn {
-    const raptor_camera* cam;
-    const raptor_grid* grid;
-    const double* nu;
-};
-
 bool plan_valid(const raptor_plan& p)
 {
     const bool tw = p.tile_width == 8 || p.tile_width == 16 || p.tile_width == 32 || p.tile_width == 64;
@@ -190,7 +184,10 @@ raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* p
     return RAPTOR_OK;
 }
 
-raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, bool mlpc = false)
+// The plan of (frequency class, precision, closure class): the installed one, else the default,
+// which is then installed unless `install` is false (the no-allocation entry point resolves the
+// default without adding it to the context's plan map).
+raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, bool mlpc = false, bool install = true)
 {
     const int key = plan_key(max_nu, fp32, mlpc);
     auto it = ctx->plans.find(key);
@@ -213,7 +210,7 @@ raptor_status plan_for(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* out, 
     }
     raptor_status s = resolve_plan(ctx, max_nu, fp32, &pl, mlpc);
     if (s != RAPTOR_OK) return s;
-    ctx->plans[key] = pl;
+    if (install) ctx->plans[key] = pl;
     *out = pl;
     return RAPTOR_OK;
 }
@@ -282,33 +279,31 @@ raptor_status launch_graph(raptor_ctx* ctx, const TraceParams& p, int n_nu, bool
     return RAPTOR_OK;
 }
 
-raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, const raptor_opts* o,
-                       double* images, double* flux_jy, int32_t* ray_status, int32_t* ray_steps, raptor_stats* st,
-                       const LaunchPlan* force_plan = nullptr)
-{
-    const bool dev = o->mem == RAPTOR_MEM_DEVICE;
-    const bool fp32 = o->transfer_prec == RAPTOR_F32;
-    const bool mlpc = o->closure >= RAPTOR_CLOSURE_MLP;
-    LaunchPlan plan;
-    if (force_plan) {
-        plan = *force_plan;
-    } else {
-        raptor_status ps = plan_for(ctx, n_nu, fp32, &plan, mlpc);
-        if (ps != RAPTOR_OK) return ps;
-    }
-    const int tile_w = plan.p.tile_width, tile_h = 64 / tile_w;
-    const int nj = (int)in.size();
-    // ---- job table
-    std::vector<DevJob> jobs(nj);
-    std::vector<const raptor_grid*> gl;
-    std::vector<double> nus, pixsr(nj);
+// Host-side tables of a launch: one DevJob per image, the distinct grids (with this call's
+// code-unit scales), the frequencies and the pixel solid angles.  The arrays belong to the
+// caller (capacities: nj, nj, nj, nj * n_nu, nj).
+struct HostTables {
+    DevJob* jobs;
+    DevGrid* grids;
+    const raptor_grid** gl;
+    double* nus;
+    double* pixsr;
+    int n_grids = 0;
     long long tiles = 0, outn = 0, pixn = 0;
+};
+
+raptor_status fill_tables(raptor_ctx* ctx, const JobIn* in, int nj, int n_nu, const raptor_opts* o, int tile_w,
+                          HostTables* t)
+{
+    const int tile_h = 64 / tile_w;
     const double M = o->metric_mass;
     const double Lu = kG * o->mass_msun * kMsun / (kC * kC);
     const double D = o->dist_pc * kPc;
+    t->n_grids = 0;
+    t->tiles = t->outn = t->pixn = 0;
     for (int k = 0; k < nj; ++k) {
         const raptor_camera& c = *in[k].cam;
-        DevJob& J = jobs[k];
+        DevJob& J = t->jobs[k];
         std::memset(&J, 0, sizeof J);
         J.a = c.spin;
         J.incl = c.incl_deg * kPi / 180.0;
@@ -324,15 +319,16 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
         J.ny = c.ny;
         J.tiles_x = (c.nx + tile_w - 1) / tile_w;
         J.n_nu = n_nu;
-        J.tile_base = tiles;
-        J.out_base = outn;
-        J.pix_base = pixn;
-        tiles += (long long)J.tiles_x * ((c.ny + tile_h - 1) / tile_h);
-        outn += (long long)n_nu * c.nx * c.ny;
-        pixn += (long long)c.nx * c.ny;
-        auto gi = std::find(gl.begin(), gl.end(), in[k].grid);
-        J.grid = (int)(gi - gl.begin());
-        if (gi == gl.end()) gl.push_back(in[k].grid);
+        J.tile_base = t->tiles;
+        J.out_base = t->outn;
+        J.pix_base = t->pixn;
+        t->tiles += (long long)J.tiles_x * ((c.ny + tile_h - 1) / tile_h);
+        t->outn += (long long)n_nu * c.nx * c.ny;
+        t->pixn += (long long)c.nx * c.ny;
+        int gi = 0;
+        while (gi < t->n_grids && t->gl[gi] != in[k].grid) ++gi;
+        if (gi == t->n_grids) t->gl[t->n_grids++] = in[k].grid;
+        J.grid = gi;
         const DevGrid& G = in[k].grid->d;
         int fs = 0;
         if (G.n_snap > 1) {
@@ -340,78 +336,77 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
             fs = std::min(std::max(fs, 0), G.n_snap - 1);
         }
         J.fast_snap = fs;
-        J.nu_base = (int)nus.size();
-        for (int f = 0; f < n_nu; ++f) nus.push_back(in[k].nu[f]);
-        pixsr[k] = J.dalpha * J.dbeta * Lu * Lu / (D * D);
+        J.nu_base = k * n_nu;
+        for (int f = 0; f < n_nu; ++f) t->nus[k * n_nu + f] = in[k].nu[f];
+        t->pixsr[k] = J.dalpha * J.dbeta * Lu * Lu / (D * D);
     }
-    if (tiles >= (1ll << 31) - 1) return fail(ctx, RAPTOR_E_RANGE, "too many pixels in one call");
-    std::vector<DevGrid> grids(gl.size());
-    for (size_t i = 0; i < gl.size(); ++i) {
-        grids[i] = gl[i]->d;
-        if (grids[i].units) {
+    if (t->tiles >= (1ll << 31) - 1) return fail(ctx, RAPTOR_E_RANGE, "too many pixels in one call");
+    for (int i = 0; i < t->n_grids; ++i) {
+        t->grids[i] = t->gl[i]->d;
+        if (t->grids[i].units) {
             // code-unit scales of this call's black-hole mass: rho0 = M / L^3
-            const double rho0 = gl[i]->mass_unit_g / (Lu * Lu * Lu);
-            grids[i].ne_scale = rho0 / (pl::ME_CGS + pl::MP_CGS);
-            grids[i].b_scale = kC * std::sqrt(4.0 * kPi * rho0);
+            const double rho0 = t->gl[i]->mass_unit_g / (Lu * Lu * Lu);
+            t->grids[i].ne_scale = rho0 / (pl::ME_CGS + pl::MP_CGS);
+            t->grids[i].b_scale = kC * std::sqrt(4.0 * kPi * rho0);
         }
     }
+    return RAPTOR_OK;
+}
 
-    // ---- device buffers
-    RAPTOR_CK(ctx->jobs.reserve(nj), "allocating the job table");
-    RAPTOR_CK(ctx->grids.reserve(grids.size()), "allocating the grid table");
-    RAPTOR_CK(ctx->nu.reserve(nus.size()), "allocating frequencies");
-    RAPTOR_CK(ctx->pixsr.reserve(nj), "allocating solid angles");
-    RAPTOR_CK(ctx->flux.reserve((size_t)nj * n_nu), "allocating fluxes");
-    RAPTOR_CK(ctx->flux_part.reserve(flux_partials(nj, n_nu)), "allocating flux partial sums");
-    double* out = nullptr;
-    if (dev && images) {
-        out = images;
-    } else {
-        RAPTOR_CK(ctx->out.reserve(outn), "allocating intensities");
-        out = ctx->out.p;
-    }
-    int* rs = nullptr;
-    int* rn = nullptr;
-    if (ray_status || ray_steps) {
-        if (dev) {
-            rs = ray_status;
-            rn = ray_steps;
-        } else {
-            RAPTOR_CK(ctx->status.reserve(pixn), "allocating ray info");
-            RAPTOR_CK(ctx->steps.reserve(pixn), "allocating ray info");
-            rs = ray_status ? ctx->status.p : nullptr;
-            rn = ray_steps ? ctx->steps.p : nullptr;
-        }
-    }
+// Device buffers of a launch: the tables, the outputs the kernels write, the tile counter and
+// the statistics.
+struct DevTables {
+    DevJob* jobs;
+    DevGrid* grids;
+    double* nu;
+    double* pixsr;
+    double* flux;
+    double* flux_part;
+    unsigned int* counter;
+    unsigned long long* stats;
+    double* out;
+    int* rs;
+    int* rn;
+};
+
+// Upload the tables, launch (reset, trace, flux; direct or as a replayed graph), copy the
+// outputs the caller wants where it wants them, wait, and fill the statistics.
+raptor_status launch_tables(raptor_ctx* ctx, const HostTables& h, const DevTables& d, int nj, int n_nu,
+                            const raptor_opts* o, const LaunchPlan& plan, double* images, double* flux_jy,
+                            int32_t* ray_status, int32_t* ray_steps, raptor_stats* st)
+{
+    const bool dev = o->mem == RAPTOR_MEM_DEVICE;
+    const bool fp32 = o->transfer_prec == RAPTOR_F32;
+    const int tile_w = plan.p.tile_width;
     hipStream_t s = ctx->stream;
-    RAPTOR_CK(hipMemcpyAsync(ctx->jobs.p, jobs.data(), nj * sizeof(DevJob), hipMemcpyHostToDevice, s), "uploading jobs");
-    RAPTOR_CK(hipMemcpyAsync(ctx->grids.p, grids.data(), grids.size() * sizeof(DevGrid), hipMemcpyHostToDevice, s),
+    RAPTOR_CK(hipMemcpyAsync(d.jobs, h.jobs, nj * sizeof(DevJob), hipMemcpyHostToDevice, s), "uploading jobs");
+    RAPTOR_CK(hipMemcpyAsync(d.grids, h.grids, h.n_grids * sizeof(DevGrid), hipMemcpyHostToDevice, s),
               "uploading the grid table");
-    RAPTOR_CK(hipMemcpyAsync(ctx->nu.p, nus.data(), nus.size() * sizeof(double), hipMemcpyHostToDevice, s),
+    RAPTOR_CK(hipMemcpyAsync(d.nu, h.nus, (size_t)nj * n_nu * sizeof(double), hipMemcpyHostToDevice, s),
               "uploading frequencies");
-    RAPTOR_CK(hipMemcpyAsync(ctx->pixsr.p, pixsr.data(), nj * sizeof(double), hipMemcpyHostToDevice, s),
+    RAPTOR_CK(hipMemcpyAsync(d.pixsr, h.pixsr, nj * sizeof(double), hipMemcpyHostToDevice, s),
               "uploading solid angles");
 
     TraceParams p;
     std::memset(&p, 0, sizeof p);   // padding included: the graph key compares the bytes
-    p.jobs = ctx->jobs.p;
-    p.grids = ctx->grids.p;
-    p.nu = ctx->nu.p;
-    p.out = out;
-    p.ray_status = rs;
-    p.ray_steps = rn;
-    p.tile_counter = ctx->counter.p;
-    p.stats = ctx->stats.p;
+    p.jobs = d.jobs;
+    p.grids = d.grids;
+    p.nu = d.nu;
+    p.out = d.out;
+    p.ray_status = d.rs;
+    p.ray_steps = d.rn;
+    p.tile_counter = d.counter;
+    p.stats = d.stats;
     p.k2 = ctx->k2t;
-    p.n_tiles = tiles;
+    p.n_tiles = h.tiles;
     p.n_jobs = nj;
     p.max_steps = o->max_steps;
     p.closure = o->closure;
     p.slow_light = o->slow_light;
     p.integrator = o->integrator;
     p.eps = o->eps;
-    p.M = M;
-    p.length_unit = Lu;
+    p.M = o->metric_mass;
+    p.length_unit = kG * o->mass_msun * kMsun / (kC * kC);
     p.const_j = o->const_j;
     p.const_alpha = o->const_alpha;
     p.tau_cutoff = o->tau_cutoff;
@@ -422,29 +417,28 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
     p.tile_shift = tile_w == 8 ? 3 : tile_w == 16 ? 4 : tile_w == 32 ? 5 : 6;
 
     if (o->launch == RAPTOR_LAUNCH_GRAPH) {
-        raptor_status gs = launch_graph(ctx, p, n_nu, fp32, plan, nj, out);
+        raptor_status gs = launch_graph(ctx, p, n_nu, fp32, plan, nj, d.out);
         if (gs != RAPTOR_OK) return gs;
     } else {
-        RAPTOR_CK(launch_reset(ctx->counter.p, ctx->stats.p, s), "launching reset");
+        RAPTOR_CK(launch_reset(d.counter, d.stats, s), "launching reset");
         RAPTOR_CK(hipEventRecord(ctx->ev0, s), "recording an event");
         RAPTOR_CK(launch_trace(p, n_nu, fp32, plan.p.min_waves_per_simd, plan.blocks, plan.p.threads, s),
                   "launching the trace kernel");
         RAPTOR_CK(hipEventRecord(ctx->ev1, s), "recording an event");
-        RAPTOR_CK(launch_flux(ctx->jobs.p, nj, out, ctx->pixsr.p, ctx->flux_part.p, ctx->flux.p, n_nu, s),
-                  "launching the flux reduction");
+        RAPTOR_CK(launch_flux(d.jobs, nj, d.out, d.pixsr, d.flux_part, d.flux, n_nu, s), "launching the flux reduction");
     }
 
     const hipMemcpyKind d2x = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (images && out != images)
-        RAPTOR_CK(hipMemcpyAsync(images, out, outn * sizeof(double), d2x, s), "copying images");
-    if (flux_jy)
-        RAPTOR_CK(hipMemcpyAsync(flux_jy, ctx->flux.p, (size_t)nj * n_nu * sizeof(double), d2x, s), "copying fluxes");
-    if (ray_status && rs != ray_status)
-        RAPTOR_CK(hipMemcpyAsync(ray_status, rs, pixn * sizeof(int), d2x, s), "copying ray status");
-    if (ray_steps && rn != ray_steps)
-        RAPTOR_CK(hipMemcpyAsync(ray_steps, rn, pixn * sizeof(int), d2x, s), "copying ray steps");
+    if (images && d.out != images)
+        RAPTOR_CK(hipMemcpyAsync(images, d.out, h.outn * sizeof(double), d2x, s), "copying images");
+    if (flux_jy && d.flux != flux_jy)
+        RAPTOR_CK(hipMemcpyAsync(flux_jy, d.flux, (size_t)nj * n_nu * sizeof(double), d2x, s), "copying fluxes");
+    if (ray_status && d.rs != ray_status)
+        RAPTOR_CK(hipMemcpyAsync(ray_status, d.rs, h.pixn * sizeof(int), d2x, s), "copying ray status");
+    if (ray_steps && d.rn != ray_steps)
+        RAPTOR_CK(hipMemcpyAsync(ray_steps, d.rn, h.pixn * sizeof(int), d2x, s), "copying ray steps");
     unsigned long long hs[ST_COUNT];
-    RAPTOR_CK(hipMemcpyAsync(hs, ctx->stats.p, sizeof hs, hipMemcpyDeviceToHost, s), "copying statistics");
+    RAPTOR_CK(hipMemcpyAsync(hs, d.stats, sizeof hs, hipMemcpyDeviceToHost, s), "copying statistics");
     RAPTOR_CK(hipStreamSynchronize(s), "running the trace");
     if (st) {
         st->rays = hs[ST_RAYS];
@@ -463,6 +457,57 @@ raptor_status run_jobs(raptor_ctx* ctx, const std::vector<JobIn>& in, int n_nu, 
         st->kernel_ms = ms;
     }
     return RAPTOR_OK;
+}
+
+raptor_status run_jobs(raptor_ctx* ctx, const JobIn* in, int nj, int n_nu, const raptor_opts* o, double* images,
+                       double* flux_jy, int32_t* ray_status, int32_t* ray_steps, raptor_stats* st,
+                       const LaunchPlan* force_plan = nullptr)
+{
+    const bool dev = o->mem == RAPTOR_MEM_DEVICE;
+    const bool fp32 = o->transfer_prec == RAPTOR_F32;
+    const bool mlpc = o->closure >= RAPTOR_CLOSURE_MLP;
+    LaunchPlan plan;
+    if (force_plan) {
+        plan = *force_plan;
+    } else {
+        raptor_status ps = plan_for(ctx, n_nu, fp32, &plan, mlpc);
+        if (ps != RAPTOR_OK) return ps;
+    }
+    std::vector<DevJob> jobs(nj);
+    std::vector<DevGrid> grids(nj);
+    std::vector<const raptor_grid*> gl(nj);
+    std::vector<double> nus((size_t)nj * n_nu), pixsr(nj);
+    HostTables h{jobs.data(), grids.data(), gl.data(), nus.data(), pixsr.data()};
+    raptor_status fs = fill_tables(ctx, in, nj, n_nu, o, plan.p.tile_width, &h);
+    if (fs != RAPTOR_OK) return fs;
+
+    // ---- device buffers of the context, grown on demand
+    RAPTOR_CK(ctx->jobs.reserve(nj), "allocating the job table");
+    RAPTOR_CK(ctx->grids.reserve(h.n_grids), "allocating the grid table");
+    RAPTOR_CK(ctx->nu.reserve((size_t)nj * n_nu), "allocating frequencies");
+    RAPTOR_CK(ctx->pixsr.reserve(nj), "allocating solid angles");
+    RAPTOR_CK(ctx->flux.reserve((size_t)nj * n_nu), "allocating fluxes");
+    RAPTOR_CK(ctx->flux_part.reserve(flux_partials(nj, n_nu)), "allocating flux partial sums");
+    DevTables d{ctx->jobs.p, ctx->grids.p, ctx->nu.p, ctx->pixsr.p, ctx->flux.p, ctx->flux_part.p,
+                ctx->counter.p, ctx->stats.p, nullptr, nullptr, nullptr};
+    if (dev && images) {
+        d.out = images;
+    } else {
+        RAPTOR_CK(ctx->out.reserve(h.outn), "allocating intensities");
+        d.out = ctx->out.p;
+    }
+    if (ray_status || ray_steps) {
+        if (dev) {
+            d.rs = ray_status;
+            d.rn = ray_steps;
+        } else {
+            RAPTOR_CK(ctx->status.reserve(h.pixn), "allocating ray info");
+            RAPTOR_CK(ctx->steps.reserve(h.pixn), "allocating ray info");
+            d.rs = ray_status ? ctx->status.p : nullptr;
+            d.rn = ray_steps ? ctx->steps.p : nullptr;
+        }
+    }
+    return launch_tables(ctx, h, d, nj, n_nu, o, plan, images, flux_jy, ray_status, ray_steps, st);
 }
 
 raptor_status check_nu(raptor_ctx* ctx, const double* nu, int n_nu)
@@ -524,6 +569,10 @@ raptor_status raptor_create(int device, void* hip_stream, raptor_ctx** out)
         return bail(dev_fail(ctx, e, "allocating counters"));
     raptor_status s = build_k2_table(ctx);
     if (s != RAPTOR_OK) return bail(s);
+    // the no-allocation entry point's device scratch on this device (current) and its host tables
+    e = noalloc_scratch_address(device, &ctx->noalloc_scratch);
+    if (e != hipSuccess) return bail(dev_fail(ctx, e, "looking up the no-allocation scratch"));
+    ctx->noalloc_host = new rctx::NoAllocHost();
     *out = ctx;
     return RAPTOR_OK;
 }
@@ -557,6 +606,7 @@ void raptor_destroy(raptor_ctx* ctx)
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx->noalloc_host;
     delete ctx;
 }
 
@@ -717,8 +767,8 @@ raptor_status raptor_trace_spectrum_ex(raptor_ctx* ctx, const raptor_camera* cam
     if ((s = check_nu(ctx, nu_hz, n_nu)) != RAPTOR_OK) return s;
     if ((s = check_camera(ctx, cam, grid, opts, 0)) != RAPTOR_OK) return s;
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
-    std::vector<JobIn> in{{cam, grid, nu_hz}};
-    return run_jobs(ctx, in, n_nu, opts, images, flux_jy, ray_status, ray_steps, stats);
+    const JobIn in{cam, grid, nu_hz};
+    return run_jobs(ctx, &in, 1, n_nu, opts, images, flux_jy, ray_status, ray_steps, stats);
 }
 
 raptor_status raptor_trace_spectrum(raptor_ctx* ctx, const raptor_camera* cam, const raptor_grid* grid,
@@ -737,18 +787,25 @@ raptor_status raptor_trace_image(raptor_ctx* ctx, const raptor_camera* cam, cons
 
 static raptor_status batch_inputs(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
                                   const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz,
-                                  int32_t n_nu, std::vector<JobIn>* in)
+                                  int32_t n_nu, JobIn* in)
+{
+    raptor_status s;
+    for (int k = 0; k < n_cams; ++k) {
+        if ((s = check_nu(ctx, nu_hz + (size_t)k * n_nu, n_nu)) != RAPTOR_OK) return s;
+        if ((s = check_camera(ctx, &cams[k], grids[k], opts, k)) != RAPTOR_OK) return s;
+        in[k] = {&cams[k], grids[k], nu_hz + (size_t)k * n_nu};
+    }
+    return RAPTOR_OK;
+}
+
+// The checks of a batch call before its inputs are read.
+static raptor_status batch_precheck(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                    const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz)
 {
     raptor_status s;
     if (!cams || !grids || n_cams < 1) return fail(ctx, RAPTOR_E_INVALID, "need n_cams >= 1 cameras and grids");
     if ((s = check_opts(ctx, opts)) != RAPTOR_OK) return s;
     if (!nu_hz) return fail(ctx, RAPTOR_E_INVALID, "nu_hz is NULL");
-    in->resize(n_cams);
-    for (int k = 0; k < n_cams; ++k) {
-        if ((s = check_nu(ctx, nu_hz + (size_t)k * n_nu, n_nu)) != RAPTOR_OK) return s;
-        if ((s = check_camera(ctx, &cams[k], grids[k], opts, k)) != RAPTOR_OK) return s;
-        (*in)[k] = {&cams[k], grids[k], nu_hz + (size_t)k * n_nu};
-    }
     return RAPTOR_OK;
 }
 
@@ -758,11 +815,65 @@ raptor_status raptor_trace_batch(raptor_ctx* ctx, const raptor_camera* cams, int
 {
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
-    std::vector<JobIn> in;
-    raptor_status s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, &in);
+    raptor_status s = batch_precheck(ctx, cams, n_cams, grids, opts, nu_hz);
+    if (s != RAPTOR_OK) return s;
+    std::vector<JobIn> in(n_cams);
+    s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, in.data());
     if (s != RAPTOR_OK) return s;
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
-    return run_jobs(ctx, in, n_nu, opts, images, flux_jy, nullptr, nullptr, stats);
+    return run_jobs(ctx, in.data(), n_cams, n_nu, opts, images, flux_jy, nullptr, nullptr, stats);
+}
+
+raptor_status raptor_trace_batch_noalloc(raptor_ctx* ctx, const raptor_camera* cams, int32_t n_cams,
+                                         const raptor_grid* const* grids, const raptor_opts* opts, const double* nu_hz,
+                                         int32_t n_nu, double* images, double* flux_jy, raptor_stats* stats)
+{
+    static_assert(rctx::NOALLOC_JOBS == NOALLOC_MAX_JOBS && RAPTOR_NOALLOC_MAX_CAMS == NOALLOC_MAX_JOBS,
+                  "one limit for the host tables and the device scratch");
+    static_assert(RAPTOR_MAX_NU <= 32, "the device scratch holds 32 frequencies per image");
+    if (!ctx) return RAPTOR_E_INVALID;
+    ctx->err.clear();
+    raptor_status s = batch_precheck(ctx, cams, n_cams, grids, opts, nu_hz);
+    if (s != RAPTOR_OK) return s;
+    if (n_cams > NOALLOC_MAX_JOBS)
+        return fail(ctx, RAPTOR_E_RANGE, "raptor_trace_batch_noalloc takes at most RAPTOR_NOALLOC_MAX_CAMS (256) cameras");
+    if (opts->mem != RAPTOR_MEM_DEVICE || !images)
+        return fail(ctx, RAPTOR_E_INVALID,
+                    "raptor_trace_batch_noalloc writes device outputs: needs opts->mem = RAPTOR_MEM_DEVICE and images");
+    if (opts->launch != RAPTOR_LAUNCH_DIRECT)
+        return fail(ctx, RAPTOR_E_UNSUPPORTED, "raptor_trace_batch_noalloc launches directly (RAPTOR_LAUNCH_DIRECT)");
+    if (!ctx->noalloc_scratch || !ctx->noalloc_host)
+        return fail(ctx, RAPTOR_E_DEVICE, "the context has no no-allocation scratch");
+    rctx::NoAllocHost& na = *ctx->noalloc_host;
+    if ((s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, na.in)) != RAPTOR_OK) return s;
+    RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
+    const bool fp32 = opts->transfer_prec == RAPTOR_F32;
+    LaunchPlan plan;
+    if ((s = plan_for(ctx, n_nu, fp32, &plan, opts->closure >= RAPTOR_CLOSURE_MLP, false)) != RAPTOR_OK) return s;
+    HostTables h{na.jobs, na.grids, na.gl, na.nus, na.pixsr};
+    if ((s = fill_tables(ctx, na.in, n_cams, n_nu, opts, plan.p.tile_width, &h)) != RAPTOR_OK) return s;
+    // the launch's buffers, carved from the scratch in 256-byte aligned regions
+    unsigned char* base = static_cast<unsigned char*>(ctx->noalloc_scratch);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* q = base + off;
+        off += noalloc_round(bytes);
+        return q;
+    };
+    DevTables d;
+    d.counter = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int)));
+    d.stats = reinterpret_cast<unsigned long long*>(take(ST_COUNT * sizeof(unsigned long long)));
+    d.jobs = reinterpret_cast<DevJob*>(take(n_cams * sizeof(DevJob)));
+    d.grids = reinterpret_cast<DevGrid*>(take(h.n_grids * sizeof(DevGrid)));
+    d.nu = reinterpret_cast<double*>(take((size_t)n_cams * n_nu * sizeof(double)));
+    d.pixsr = reinterpret_cast<double*>(take(n_cams * sizeof(double)));
+    d.flux = flux_jy ? flux_jy : reinterpret_cast<double*>(take((size_t)n_cams * n_nu * sizeof(double)));
+    d.flux_part = reinterpret_cast<double*>(take(flux_partials(n_cams, n_nu) * sizeof(double)));
+    d.out = images;
+    d.rs = nullptr;
+    d.rn = nullptr;
+    if (off > NOALLOC_SCRATCH_BYTES) return fail(ctx, RAPTOR_E_RANGE, "the batch exceeds the no-allocation scratch");
+    return launch_tables(ctx, h, d, n_cams, n_nu, opts, plan, images, flux_jy, nullptr, nullptr, stats);
 }
 
 raptor_status raptor_get_plan(raptor_ctx* ctx, int32_t n_nu, int32_t transfer_prec, int32_t closure,
@@ -806,8 +917,10 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
 {
     if (!ctx) return RAPTOR_E_INVALID;
     ctx->err.clear();
-    std::vector<JobIn> in;
-    raptor_status s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, &in);
+    raptor_status s = batch_precheck(ctx, cams, n_cams, grids, opts, nu_hz);
+    if (s != RAPTOR_OK) return s;
+    std::vector<JobIn> in(n_cams);
+    s = batch_inputs(ctx, cams, n_cams, grids, opts, nu_hz, n_nu, in.data());
     if (s != RAPTOR_OK) return s;
     if (reps < 1 || reps > 100) return fail(ctx, RAPTOR_E_INVALID, "reps must be in [1, 100]");
     RAPTOR_CK(hipSetDevice(ctx->device), "selecting the device");
@@ -822,7 +935,7 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
         double bestv = 1e300;
         for (int i = 0; i < reps; ++i) {
             raptor_stats st;
-            r = run_jobs(ctx, in, n_nu, &o, nullptr, nullptr, nullptr, nullptr, &st, &pl);
+            r = run_jobs(ctx, in.data(), n_cams, n_nu, &o, nullptr, nullptr, nullptr, nullptr, &st, &pl);
             if (r != RAPTOR_OK) return r;
             bestv = std::min(bestv, st.kernel_ms);
         }

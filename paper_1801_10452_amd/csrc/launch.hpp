@@ -9,6 +9,8 @@ hipError_t launch_reset(unsigned int* tile_counter, unsigned long long* stats, h
 hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, int blocks, int threads,
                         hipStream_t st);
 // flux in two deterministic passes through flux_partials(n_jobs, max_nu) partial sums
+// (FLUX_SPLIT per job and frequency)
+constexpr int FLUX_SPLIT = 16;
 size_t flux_partials(int n_jobs, int max_nu);
 hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const double* pix_sr, double* part,
                        double* flux, int max_nu, hipStream_t st);
@@ -48,3 +50,19 @@ hipError_t mlp_launch_forward(const mlp::Net& net, bool split, const float* X, l
 hipError_t mlp_launch_forward_f32(const float* P, const float* X, long long n, float* Y, hipStream_t st);
 hipError_t mlp_launch_backward_f32(const float* P, const float* X, const float* DY, long long n, float* G,
                                    hipStream_t st);
+
+// ---- the no-allocation batch entry point (noalloc.hip)
+// Device scratch of raptor_trace_batch_noalloc: a fixed array per GPU holding the tile counter,
+// the statistics, the job, grid, frequency and solid-angle tables, the fluxes when the caller
+// passes none, and the flux partial sums, each region aligned to 256 bytes, for at most
+// NOALLOC_MAX_JOBS images of up to RAPTOR_MAX_NU frequencies.
+constexpr int NOALLOC_MAX_JOBS = 256;
+constexpr size_t noalloc_round(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    noalloc_round(sizeof(unsigned int)) + noalloc_round(ST_COUNT * sizeof(unsigned long long)) +
+    noalloc_round(NOALLOC_MAX_JOBS * sizeof(DevJob)) + noalloc_round(NOALLOC_MAX_JOBS * sizeof(DevGrid)) +
+    2 * noalloc_round((size_t)NOALLOC_MAX_JOBS * 32 * sizeof(double)) + noalloc_round(NOALLOC_MAX_JOBS * sizeof(double)) +
+    noalloc_round((size_t)NOALLOC_MAX_JOBS * 32 * FLUX_SPLIT * sizeof(double));
+// Device address of this process's scratch array on `device` (which must be current): looked
+// up once per device with hipGetSymbolAddress and kept.
+hipError_t noalloc_scratch_address(int device, void** ptr);

@@ -649,7 +649,6 @@ trace_kernel(TraceParams p)
 // summing the pixels b * 256 + t + k * 256 * FLUX_SPLIT of every thread t in order and
 // combining its threads in a fixed tree.  Pass 2: one thread per (job, frequency) adds the
 // FLUX_SPLIT partial sums in order.  The result does not depend on scheduling.
-constexpr int FLUX_SPLIT = 16;
 
 __global__ void __launch_bounds__(256) flux_partial_kernel(const DevJob* jobs, const double* out, double* part,
                                                            int max_nu)

@@ -25,6 +25,7 @@ RK4, RK2, VERLET, VERLET_CORRECTED = 0, 1, 2, 3
 MLP_PARAMS = 12866
 RAY_HORIZON, RAY_ESCAPED, RAY_MAXSTEP, RAY_NUMERIC = 1, 2, 3, 4
 MAX_NU = 32
+RAPTOR_NOALLOC_MAX_CAMS = 256
 
 DP = C.POINTER(C.c_double)
 IP = C.POINTER(C.c_int32)
@@ -94,7 +95,7 @@ class CMlpReport(C.Structure):
 # every symbol include/raptor.h declares
 EXPORTS = ["raptor_create", "raptor_destroy", "raptor_last_error", "raptor_grid_upload", "raptor_grid_release",
            "raptor_default_opts", "raptor_trace_image", "raptor_trace_spectrum", "raptor_trace_spectrum_ex",
-           "raptor_trace_batch", "raptor_work_per_unit", "raptor_work_per_step", "raptor_get_plan", "raptor_set_plan",
+           "raptor_trace_batch", "raptor_trace_batch_noalloc", "raptor_work_per_unit", "raptor_work_per_step", "raptor_get_plan", "raptor_set_plan",
            "raptor_isco", "raptor_trace_disk",
            "raptor_autotune_batch", "raptor_kernel_info", "raptor_mlp_default_cfg", "raptor_mlp_init",
            "raptor_mlp_train", "raptor_mlp_get_params", "raptor_mlp_set_params", "raptor_mlp_get_weights",
@@ -136,6 +137,8 @@ def lib():
                                                V, C.POINTER(CStats)]
         L.raptor_trace_batch.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts), DP,
                                          C.c_int32, V, V, C.POINTER(CStats)]
+        L.raptor_trace_batch_noalloc.argtypes = [V, C.POINTER(CCamera), C.c_int32, C.POINTER(V), C.POINTER(COpts),
+                                                 DP, C.c_int32, V, V, C.POINTER(CStats)]
         L.raptor_work_per_unit.argtypes = [DP] * 6
         L.raptor_work_per_step.argtypes = [C.c_int32, DP, DP]
         L.raptor_isco.argtypes = [C.c_double, DP]
@@ -380,6 +383,21 @@ class Context:
                                              _out(images, total, "f8", m, d, "images"),
                                              _out(flux, n * n_nu, "f8", m, d, "flux"), C.byref(st)))
         return images, flux, st
+
+
+def trace_batch_noalloc(ctx, cams, grids, nu, opts, images, flux=None):
+    """raptor_trace_batch_noalloc: as Context.trace_batch with device outputs (opts.mem =
+    MEM_DEVICE, images a CUDA tensor of all images concatenated, flux a CUDA tensor or None);
+    the call allocates nothing.  Returns the stats."""
+    n, nu, carr, garr = _batch_args(cams, grids, nu)
+    n_nu = nu.shape[1]
+    total = sum(c.nx * c.ny for c in cams) * n_nu
+    m, d = opts.mem, ctx.device
+    st = CStats()
+    ctx._check(lib().raptor_trace_batch_noalloc(ctx.h, carr, n, garr, C.byref(opts), nu.ctypes.data_as(DP), n_nu,
+                                                _out(images, total, "f8", m, d, "images"),
+                                                _out(flux, n * n_nu, "f8", m, d, "flux"), C.byref(st)))
+    return st
 
 
 def make_plan(threads=256, blocks_per_cu=0, refill_threshold=1, tile_width=8, min_waves_per_simd=2) -> CPlan:
