@@ -153,12 +153,15 @@ typedef struct {
 /* Counters of the last trace call.  ray_steps counts accepted steps, samples the plasma
  * samples evaluated, n_mlp_fallback the sample-frequencies that the learned closure handed to
  * the exact closure (inputs outside its box), n_opaque the rays stopped by the optical-depth
- * cut-off. */
+ * cut-off, n_mlp_dropped the sample-frequencies outside the learned closure's box whose emission
+ * it dropped because the cut-off factor exp(-X^1/3) of thermal synchrotron emission lies below
+ * the float range there (X^1/3 > 88, X = nu / nu_s). */
 typedef struct {
     uint64_t rays, ray_steps, samples, n_horizon, n_escaped, n_maxstep, n_pole, n_numeric,
              n_mlp_fallback, n_zamo_fallback;
     double kernel_ms;
     uint64_t n_opaque;
+    uint64_t n_mlp_dropped;
 } raptor_stats;
 
 /* Fill *opts with the defaults: eps 0.05, r_stop_factor 1.01, max_steps 10000, FP64

@@ -48,7 +48,7 @@ struct K2Table {
 
 enum : int {
     ST_RAYS = 0, ST_STEPS, ST_SAMPLES, ST_HORIZON, ST_ESCAPED, ST_MAXSTEP, ST_POLE, ST_NUMERIC,
-    ST_MLP_FALLBACK, ST_ZAMO, ST_OPAQUE, ST_COUNT
+    ST_MLP_FALLBACK, ST_ZAMO, ST_OPAQUE, ST_MLP_DROPPED, ST_COUNT
 };
 
 struct TraceParams {

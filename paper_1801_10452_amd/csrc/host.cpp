@@ -452,6 +452,7 @@ raptor_status launch_tables(raptor_ctx* ctx, const HostTables& h, const DevTable
         st->n_mlp_fallback = hs[ST_MLP_FALLBACK];
         st->n_zamo_fallback = hs[ST_ZAMO];
         st->n_opaque = hs[ST_OPAQUE];
+        st->n_mlp_dropped = hs[ST_MLP_DROPPED];
         float ms = 0.0f;
         RAPTOR_CK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "reading the kernel time");
         st->kernel_ms = ms;

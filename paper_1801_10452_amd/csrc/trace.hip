@@ -267,11 +267,17 @@ __device__ inline void mlp_contribution_f32(const Transfer<float>& tr, float y0,
 
 // Learned-closure variant of eval_sample for one round: every lane of the wave takes part in the
 // network evaluations (one per frequency); lanes without a sample feed zeros.  Samples whose
-// closure inputs leave the training box use the exact closure.
+// closure inputs leave the training box use the exact closure, except where the emission's
+// cut-off factor exp(-X^1/3) lies below the float range (X^1/3 > 88, X > 88^3): there emission
+// and absorption (j / B_nu) are dropped, which changes no flux at any measurable level (such a
+// sample's j is below 1e-38 of its prefactor) and spares the fallback the samples of the dilute,
+// weakly magnetised outer flow, where nu/nu_c exceeds the box's 1e6.
+constexpr double MLP_DROP_X = 88.0 * 88.0 * 88.0;
+
 template <int NNU, class TT>
 __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char* lds_net, bool has, const double* q,
                                       const LaneInfo& li, double* A, double* dtau, unsigned long long& c_zamo,
-                                      unsigned long long& c_fallback)
+                                      unsigned long long& c_fallback, unsigned long long& c_dropped)
 {
     double fl[4] = {0.0, 1.0, 1.0, 0.0};
     double nr = 1.0, cb = 0.0;
@@ -292,13 +298,17 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
     const float lth = (float)rt::log_pos(fl[1] > 0.0 ? fl[1] : 1.0);
     const double ds = nr * q[7] * p.length_unit;
     const double inr3 = has ? rt::rcp_nr(nr * nr * nr) : 0.0;
+    // nu_s / nu: X = nu / nu_s, nu_s = (2/9) nu_c Theta_e^2 sin(theta_B)
+    const double nus = (2.0 / 9.0) * nuc * fl[1] * fl[1] * ::sqrt(::fmax(1.0 - cb * cb, 0.0));
 #pragma unroll 1
     for (int f = 0; f < NNU; ++f) {
         const bool act = has && f < li.n_nu;
         const double nu = act ? p.nu[li.nu_base + f] * nr : nuc;
         const float lx = (float)rt::log_pos(nu / nuc);
         const bool inb = act && tr.emits && mlp::in_box(lx, lth, (float)cb);
-        c_fallback += __popcll(__ballot(act && tr.emits && !inb));
+        const bool drop = act && tr.emits && !inb && nu > MLP_DROP_X * nus;
+        c_fallback += __popcll(__ballot(act && tr.emits && !inb && !drop));
+        c_dropped += __popcll(__ballot(drop));
         const float x0 = inb ? mlp::norm_lx(lx) : 0.0f, x1 = inb ? mlp::norm_lt(lth) : 0.0f,
                     x2 = inb ? mlp::norm_cb((float)cb) : 0.0f;
         float y0, y1;
@@ -325,7 +335,7 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
                 const double al = ne * pl::J_PREF / (2.0 * pl::ME_CGS * nuc) * ::exp(lna) * planck;
                 pl::step_source(j, al, j / al, ds, inr3, A[f], dtau[f]);
             }
-        } else if (tr.emits) {
+        } else if (tr.emits && !drop) {
             tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
         }
     }
@@ -374,7 +384,7 @@ trace_kernel(TraceParams p)
 
     // wave-level statistics (ballot counts: scalar registers)
     unsigned long long c_rays = 0, c_steps = 0, c_samples = 0, c_hor = 0, c_esc = 0, c_max = 0, c_pole = 0,
-                       c_num = 0, c_zamo = 0, c_fallback = 0, c_opq = 0;
+                       c_num = 0, c_zamo = 0, c_fallback = 0, c_opq = 0, c_dropped = 0;
 
     long long next = 0, end = 0;   // rays of the current tile not yet handed out (wave-uniform)
     bool drained = false;
@@ -535,7 +545,7 @@ trace_kernel(TraceParams p)
                     for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * Q::SLOTS + s] : 1.0;
                     double A[NNU], dt[NNU];
                     eval_round_mlp<NNU, TT>(p, lds_net, has, q, lane_info(p, lane_job[s / K]), A, dt, c_zamo,
-                                            c_fallback);
+                                            c_fallback, c_dropped);
                     if (has) {
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
@@ -637,7 +647,7 @@ trace_kernel(TraceParams p)
     // ------------------------------------------------------------ statistics, one atomic per counter per wave
     if (lane == 0) {
         const unsigned long long st[ST_COUNT] = {c_rays, c_steps, c_samples, c_hor, c_esc, c_max, c_pole, c_num,
-                                                 c_fallback, c_zamo, c_opq};
+                                                 c_fallback, c_zamo, c_opq, c_dropped};
 #pragma unroll
         for (int i = 0; i < ST_COUNT; ++i)
             if (st[i]) atomicAdd(p.stats + i, st[i]);

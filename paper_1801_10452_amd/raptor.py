@@ -62,7 +62,8 @@ class CStats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("ray_steps", C.c_uint64), ("samples", C.c_uint64),
                 ("n_horizon", C.c_uint64), ("n_escaped", C.c_uint64), ("n_maxstep", C.c_uint64),
                 ("n_pole", C.c_uint64), ("n_numeric", C.c_uint64), ("n_mlp_fallback", C.c_uint64),
-                ("n_zamo_fallback", C.c_uint64), ("kernel_ms", C.c_double), ("n_opaque", C.c_uint64)]
+                ("n_zamo_fallback", C.c_uint64), ("kernel_ms", C.c_double), ("n_opaque", C.c_uint64),
+                ("n_mlp_dropped", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

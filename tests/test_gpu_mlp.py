@@ -65,18 +65,45 @@ def test_forward_independent_of_block_placement(R, ctx, orc):
             assert np.array_equal(R.mlp_forward(ctx, x[:n], form), y[:n])
 
 
+# parameter blocks of the network in the order of the parameter vector: W[out][in], then b[out]
+LAYERS = [(3, 64), (64, 64), (64, 64), (64, 64), (64, 2)]
+
+
+def param_blocks():
+    blocks, o = [], 0
+    for k, (n_in, n_out) in enumerate(LAYERS):
+        blocks.append((f"W{k}", o, o + n_in * n_out))
+        o += n_in * n_out
+        blocks.append((f"b{k}", o, o + n_out))
+        o += n_out
+    return blocks
+
+
 def test_backward_matches_oracle(R, ctx, orc):
+    """Every element of the parameter gradient against the oracle's float64 backward pass: the
+    difference of each element is bounded by a fraction of the root-mean-square gradient of its
+    own parameter block (a weight matrix or a bias vector), so that small elements of a block are
+    held to the same absolute accuracy as its large ones (FP32: 1e-4, the training form with
+    BF16 operands: 5e-2 of the block's rms), and the whole vector by its l2 error and cosine."""
     P = random_params(orc, 3, 0.15)
     R.mlp_set_params(ctx, P)
     rng = np.random.default_rng(4)
     x = rng.uniform(-1, 1, (333, 3)).astype(np.float32)
     dy = rng.normal(0, 1, (333, 2)).astype(np.float32)
     ref = orc.mlp_backward(P.astype(np.float64), x.astype(np.float64), dy.astype(np.float64))
-    for form, tol in [(R.MLP_F32, 1e-4), (R.MLP_BF16, 3e-2)]:
+    assert ref.size == sum(b - a for _, a, b in param_blocks())
+    for form, tol_el, tol in [(R.MLP_F32, 1e-4, 1e-4), (R.MLP_BF16, 5e-2, 3e-2)]:
         g = R.mlp_backward(ctx, x, dy, form).astype(np.float64)
         rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
         cos = g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref))
-        print(f"[mlp backward form={form}] rel l2 err {rel:.3e} cosine {cos:.6f}", flush=True)
+        worst = []
+        for name, a, b in param_blocks():
+            rms = np.sqrt(np.mean(ref[a:b] ** 2))
+            e = np.abs(g[a:b] - ref[a:b]) / rms
+            worst.append((e.max(), name))
+            assert e.max() <= tol_el, (form, name, e.max())
+        print(f"[mlp backward form={form}] rel l2 err {rel:.3e} cosine {cos:.6f} worst element / block rms "
+              f"{max(worst)[0]:.3e} ({max(worst)[1]})", flush=True)
         assert rel <= tol and cos >= 1 - tol
 
 
@@ -163,12 +190,18 @@ def test_mlp_closure_fp32_transfer_matches_fp64(R, ctx):
 
 def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
     """The learned closure trained with the default configuration (1e7 samples) inside the
-    production render (9 images of 512^2, FP64 geodesics, FP32 transfer): total flux within
-    1e-3 of the exact closure for every image (the exact-closure render matches the oracle per
-    pixel, see the parity tests), and more accurate than the paper's K2 ~ 2 Theta^2
-    approximation of the same closure.  Throughput of the three closures is printed."""
+    production render (9 images of 512^2, FP64 geodesics, FP32 transfer), against the method
+    without it, the exact closure: total flux within 1e-3 of the exact closure's for every image
+    (the exact-closure render matches the oracle per pixel, see the parity tests), fewer than
+    10% of the sample-frequencies handed back to the exact closure, and the cost of the
+    network against the exact closure printed.  The network gains no speed here: one
+    evaluation is some 360 matrix instructions per 64-sample round against about 150 vector
+    instructions for the exact closure with its tabulated K2, so the learned form is slower; what
+    the test asserts it does gain is accuracy over the paper's own K2 ~ 2 Theta^2 closure, which
+    it beats on every image."""
     R.mlp_init(ctx)
     rep = R.mlp_train(ctx)
+    ctx._trained = True
     print(f"[mlp default training] {rep.as_dict()}", flush=True)
     sets = S.production_set()
     cams = [c for c, _ in sets]
@@ -190,7 +223,46 @@ def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
               f"max|dF/F| {np.abs(rel).max():.3e} fallback {st.n_mlp_fallback}/{st.samples}", flush=True)
     e_mlp = np.abs(res["mlp_split"][0] / fx - 1)
     e_k2 = np.abs(res["k2_paper"][0] / fx - 1)
+    st_m, st_x = res["mlp_split"][1], res["exact"][1]
+    fb = st_m.n_mlp_fallback / st_m.samples
+    print(f"[mlp gain] learned / exact kernel time {st_m.kernel_ms / st_x.kernel_ms:.2f}; exact fallback "
+          f"{fb:.4f} of the sample-frequencies, dropped (X^1/3 > 88) {st_m.n_mlp_dropped / st_m.samples:.4f}",
+          flush=True)
     assert e_mlp.max() <= 1e-3
     assert e_mlp.max() < e_k2.min()
+    assert fb < 0.1
     for h in handles.values():
         ctx.release_grid(h)
+
+
+def test_trained_network_vlbi_and_slow_light_against_oracle_exact(R, ctx, orc):
+    """The trained network (trained here if the module's earlier test did not) at the four VLBI
+    frequencies {22, 43, 86, 230} GHz, in fast light on three 64^2 images (spins 0, 0.5, 0.9375 at
+    inclinations 85, 30, 60 on float32 128^2 grids) and in slow light on a 48^2 image of the
+    64-snapshot modulated series: every (image, frequency) total flux within 1e-3 of the
+    oracle's exact-closure flux and of the GPU exact closure's."""
+    if not getattr(ctx, "_trained", False):
+        R.mlp_init(ctx)
+        R.mlp_train(ctx)
+        ctx._trained = True
+    from tests.gpu_common import oracle_opts
+    nu = S.NU_VLBI
+    cases = []
+    for spin, incl in ((0.0, 85.0), (0.5, 30.0), (0.9375, 60.0)):
+        cases.append((S.Camera(spin=spin, incl_deg=incl, nx=64, ny=64), S.make_grid(128, 128, a_gen=spin), 0))
+    slow = S.make_grid(48, 48, a_gen=0.9375, dtype=np.float32, n_snap=64, dt_snap=10.0, mod_amp=0.2)
+    cases.append((S.Camera(spin=0.9375, incl_deg=60.0, nx=48, ny=48, t_frame=320.0), slow, 1))
+    worst_o = worst_g = 0.0
+    for cam, g, sl in cases:
+        gh = ctx.upload_grid(g)
+        _, fm, sm = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32, closure=R.CLOSURE_MLP,
+                                                                   slow_light=sl))
+        _, fx, _ = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32, slow_light=sl))
+        ctx.release_grid(gh)
+        _, fo, _ = orc.trace_image(cam, orc.GridHandle(g), oracle_opts(orc, R.default_opts(slow_light=sl)), nu)
+        eo = np.abs(np.asarray(fm) / fo - 1)
+        eg = np.abs(np.asarray(fm) / np.asarray(fx) - 1)
+        print(f"[mlp vlbi a={cam.spin} i={cam.incl_deg} slow={sl}] |dF/F| vs oracle exact {eo} vs gpu exact {eg} "
+              f"fallback {sm.n_mlp_fallback}/{sm.samples * len(nu)} dropped {sm.n_mlp_dropped}", flush=True)
+        worst_o, worst_g = max(worst_o, eo.max()), max(worst_g, eg.max())
+    assert worst_o <= 1e-3 and worst_g <= 1e-3
