@@ -148,6 +148,16 @@ typedef struct {
                                     which its optical depth from the camera is >= tau_cutoff at
                                     every frequency (Sec. 3.1: emission from further along reaches
                                     the camera attenuated by at least exp(-tau_cutoff)); 0: off */
+    double tau_step;             /* > 0: optical-depth-aware step (Sec. 3.1, backward scheme: a
+                                    geodesic and a transfer step, the smaller taken).  The transfer
+                                    step is the affine step over which the absorption of the ray's
+                                    last sample, at its most absorbing frequency, gives an optical
+                                    depth of tau_step: |dlambda| <= tau_step / max_f(alpha_f nu_r L);
+                                    no limit before the first sample or after a step without an
+                                    absorbing sample.  Each sample is then evaluated before the
+                                    next step (no sample compaction).  In opaque media combine it
+                                    with tau_cutoff: each step gains at most about tau_step of
+                                    optical depth.  0: off (the step follows the geometry alone) */
 } raptor_opts;
 
 /* Counters of the last trace call.  ray_steps counts accepted steps, samples the plasma

@@ -37,7 +37,8 @@ class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("r_stop_factor", C.c_double), ("max_steps", C.c_int32),
                 ("closure", C.c_int32), ("slow_light", C.c_int32), ("integrator", C.c_int32),
                 ("mass_msun", C.c_double), ("dist_pc", C.c_double), ("const_j", C.c_double),
-                ("const_alpha", C.c_double), ("metric_mass", C.c_double), ("tau_cutoff", C.c_double)]
+                ("const_alpha", C.c_double), ("metric_mass", C.c_double), ("tau_cutoff", C.c_double),
+                ("tau_step", C.c_double)]
 
 
 class RayInfo(C.Structure):
@@ -154,9 +155,9 @@ class GridHandle:
 
 def make_opts(eps=0.05, r_stop_factor=1.01, max_steps=10000, closure=EXACT, slow_light=0,
               mass_msun=4.5e6, dist_pc=8500.0, const_j=0.0, const_alpha=0.0, metric_mass=1.0,
-              integrator=0, tau_cutoff=0.0) -> Opts:
+              integrator=0, tau_cutoff=0.0, tau_step=0.0) -> Opts:
     return Opts(eps, r_stop_factor, max_steps, closure, slow_light, integrator, mass_msun, dist_pc,
-                const_j, const_alpha, metric_mass, tau_cutoff)
+                const_j, const_alpha, metric_mass, tau_cutoff, tau_step)
 
 
 # ------------------------------------------------------------------------------------------

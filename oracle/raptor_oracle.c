@@ -735,7 +735,15 @@ double orc_length_unit(double mass_msun) { return O_G * mass_msun * O_MSUN / (O_
  * i.e. the formal solution with coefficients constant over the step (Sec. 3.1, second
  * formal-solution equation), attenuated by the optical depth already between the point and
  * the camera (backward-transfer equation), and converted to observed intensity with the
- * invariant I/nu^3 (Sec. 3.1).  No optical-depth cut-off. */
+ * invariant I/nu^3 (Sec. 3.1).
+ *
+ * Optical-depth-aware step (Sec. 3.1, backward scheme: a step for the geodesic and one for the
+ * transfer, the smaller taken; the paper gives no rule for the transfer step).  Reading: with
+ * tau_step > 0 the transfer step is the affine step over which the absorption of the last
+ * sample, at the most absorbing traced frequency, gives an optical depth of tau_step,
+ * tau_step / max_f(alpha_f nu_r L); before the first sample, and after a step that took no
+ * sample or one without absorption, there is no transfer limit.  The optional cut-off
+ * (tau_cutoff) is applied as described below. */
 int orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o,
                   double alpha, double beta, const double* nu, int n_nu, double* Iout,
                   orc_ray_info* info, orc_step_rec* rec, int rec_cap)
@@ -751,8 +759,12 @@ int orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o
     double tau[ORC_MAX_NU];
     for (int f = 0; f < n_nu; ++f) { Iout[f] = 0.0; tau[f] = 0.0; }
     int steps = 0, samples = 0, poles = 0, status = ORC_RUNNING;
+    double rt_rate = 0.0;   /* d tau / d|lambda| at the last sample, most absorbing frequency */
     while (status == ORC_RUNNING) {
-        double dl = -orc_step_size(o->eps, y, y + 4);
+        double h = orc_step_size(o->eps, y, y + 4);
+        if (o->tau_step > 0.0 && rt_rate > 0.0) h = fmin(h, o->tau_step / rt_rate);
+        double dl = -h;
+        rt_rate = 0.0;
         geo_step(a, M, o->integrator, y, acc, &have_acc, dl, yn);
         memcpy(y, yn, sizeof y);
         ++steps;
@@ -788,6 +800,7 @@ int orc_trace_ray(const orc_camera* cam, const orc_grid* grid, const orc_opts* o
                                       : exp(-tau[f]) * jv * ds / (nr * nr * nr);
             Iout[f] += add;
             tau[f] += dtau;
+            rt_rate = fmax(rt_rate, av * nr * Lu);
             if (rr && f == 0) { rr->sampled = 1; rr->nu_r = nr; rr->j = jv; rr->alpha = av; rr->ds = ds; }
         }
         /* optical-depth cut-off (Sec. 3.1, backward scheme): once the material between the

@@ -45,6 +45,8 @@ typedef struct {
     int32_t max_steps, closure, slow_light, integrator;
     double mass_msun, dist_pc, const_j, const_alpha, metric_mass;
     double tau_cutoff;               /* > 0: stop a ray once tau >= tau_cutoff at every frequency */
+    double tau_step;                 /* > 0: optical-depth-aware step, at most tau_step of optical
+                                        depth per step at the last sample's absorption */
 } orc_opts;
 
 typedef struct {

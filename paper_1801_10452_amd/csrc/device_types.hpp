@@ -65,6 +65,7 @@ struct TraceParams {
     int n_jobs, max_steps, closure, slow_light, integrator, pad;
     int refill_threshold, tile_shift;   // tile width = 1 << tile_shift pixels, height 64 / width
     double eps, M, length_unit, const_j, const_alpha, tau_cutoff;
+    double tau_step;           // > 0: optical-depth-aware step (at most tau_step per step at the last sample)
     // learned closure (closure == CL_MLP): FP32 parameters and padded BF16 hi / lo weights
     const float* mlp_P;
     const unsigned short* mlp_W;

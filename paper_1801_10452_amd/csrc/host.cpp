@@ -102,6 +102,8 @@ raptor_status check_opts(raptor_ctx* ctx, const raptor_opts* o)
         return fail(ctx, RAPTOR_E_INVALID, "unknown integrator");
     if (!(std::isfinite(o->tau_cutoff) && o->tau_cutoff >= 0.0))
         return fail(ctx, RAPTOR_E_INVALID, "tau_cutoff must be finite and >= 0");
+    if (!(std::isfinite(o->tau_step) && o->tau_step >= 0.0))
+        return fail(ctx, RAPTOR_E_INVALID, "tau_step must be finite and >= 0");
     if (o->integrator != RAPTOR_RK4 && o->closure >= RAPTOR_CLOSURE_MLP)
         return fail(ctx, RAPTOR_E_UNSUPPORTED, "the learned closure runs with the RK4 integrator only");
     if (!finite_pos(o->mass_msun) || !finite_pos(o->dist_pc))
@@ -410,6 +412,7 @@ raptor_status launch_tables(raptor_ctx* ctx, const HostTables& h, const DevTable
     p.const_j = o->const_j;
     p.const_alpha = o->const_alpha;
     p.tau_cutoff = o->tau_cutoff;
+    p.tau_step = o->tau_step;
     p.mlp_P = ctx->mlp.P.p;
     p.mlp_W = ctx->mlp.W.p;
     p.mlp_Wlo = ctx->mlp.Wlo.p;

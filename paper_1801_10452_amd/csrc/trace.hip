@@ -372,6 +372,9 @@ trace_kernel(TraceParams p)
     double vacc[4] = {0.0, 0.0, 0.0, 0.0};
     bool have_acc = false;
     double a = 0.0, r_stop = 0.0, r_esc = 0.0, sth = 0.0, cth = 1.0;
+    // optical-depth-aware step: d tau / d|lambda| of the last sample at its most absorbing
+    // frequency (0: no transfer limit on the next step)
+    double rt_rate = 0.0;
     int job = 0, steps = 0, pix = 0, n_nu = 0, grid = 0, pending = 0;
     int qstep[K];   // step number of each queued sample (the optical-depth cut-off ends the ray there)
     bool active = false;
@@ -433,6 +436,7 @@ trace_kernel(TraceParams p)
                         grid = J.grid;
                         lane_job[lane] = job;
                         steps = 0;
+                        rt_rate = 0.0;
                         have_acc = false;
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) { I[f] = 0.0; tau[f] = 0.0; }
@@ -453,7 +457,10 @@ trace_kernel(TraceParams p)
         int status = RAY_RUNNING;
         if (active) {
             const rk::Spin<double> sp = rk::make_spin(a, M);
-            const double dl = -rk::step_size(p.eps, y);
+            double h = rk::step_size(p.eps, y);
+            if (p.tau_step > 0.0 && rt_rate > 0.0) h = ::fmin(h, p.tau_step / rt_rate);
+            rt_rate = 0.0;
+            const double dl = -h;
             const double th0 = y[2], s0 = sth, c0 = cth;
             if (INTEG == INTEG_RK2) {
                 rk::rk2_step(sp, y, dl, sth, cth);
@@ -511,8 +518,9 @@ trace_kernel(TraceParams p)
         unsigned total = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) total += __popcll(__ballot(pending > k));
-        // a ray that ends with queued samples needs all of them now; a full queue needs one slot
-        const bool ending = __ballot(status != RAY_RUNNING && pending > 0) != 0ull;
+        // a ray that ends with queued samples needs all of them now; a full queue needs one slot;
+        // with the optical-depth-aware step every sample is needed before its ray's next step
+        const bool ending = __ballot(status != RAY_RUNNING && pending > 0) != 0ull || (p.tau_step > 0.0 && total > 0);
         const bool full = __ballot(pending == K) != 0ull;
         if (ending || full || total >= 64) {
             // whole rounds when there are 64 or more (the oldest samples, so a full queue always
@@ -581,15 +589,18 @@ trace_kernel(TraceParams p)
             for (int k = 0; k < K; ++k) {
                 if (k < take && !cut) {
                     const int s = lane * K + k;
-                    double tmin = 1e300;
+                    double tmin = 1e300, dtmax = 0.0;
 #pragma unroll
                     for (int f = 0; f < NNU; ++f) {
                         if (f < n_nu) {
                             I[f] = I[f] + (double)attenuation<TT>(tau[f]) * res[s * 2 * NNU + f];
                             tau[f] = tau[f] + res[s * 2 * NNU + NNU + f];
                             tmin = ::fmin(tmin, tau[f]);
+                            dtmax = ::fmax(dtmax, res[s * 2 * NNU + NNU + f]);
                         }
                     }
+                    // d tau / d|lambda| of this sample (the last one folded sets the next step)
+                    if (p.tau_step > 0.0) rt_rate = dtmax / fields[7 * Q::SLOTS + s];
                     if (p.tau_cutoff > 0.0 && tmin >= p.tau_cutoff) {
                         cut = true;
                         status = RAY_OPAQUE;

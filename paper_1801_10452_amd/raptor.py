@@ -55,7 +55,8 @@ class COpts(C.Structure):
                 ("transfer_prec", C.c_int32), ("closure", C.c_int32), ("slow_light", C.c_int32), ("mem", C.c_int32),
                 ("launch", C.c_int32), ("mass_msun", C.c_double), ("dist_pc", C.c_double),
                 ("const_j", C.c_double), ("const_alpha", C.c_double), ("metric_mass", C.c_double),
-                ("integrator", C.c_int32), ("reserved", C.c_int32), ("tau_cutoff", C.c_double)]
+                ("integrator", C.c_int32), ("reserved", C.c_int32), ("tau_cutoff", C.c_double),
+                ("tau_step", C.c_double)]
 
 
 class CStats(C.Structure):

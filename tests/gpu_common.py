@@ -26,7 +26,7 @@ def oracle_opts(orc, o):
     return orc.make_opts(eps=o.eps, r_stop_factor=o.r_stop_factor, max_steps=o.max_steps, closure=o.closure,
                          slow_light=o.slow_light, mass_msun=o.mass_msun, dist_pc=o.dist_pc, const_j=o.const_j,
                          const_alpha=o.const_alpha, metric_mass=o.metric_mass, integrator=o.integrator,
-                         tau_cutoff=o.tau_cutoff)
+                         tau_cutoff=o.tau_cutoff, tau_step=o.tau_step)
 
 
 def sample_pixels(cam, n, seed):

@@ -34,7 +34,7 @@ def test_struct_sizes_match_header_layout(tmp_path):
     import subprocess
     from paper_1801_10452_amd import raptor as R
     assert ctypes.sizeof(R.CCamera) == 48
-    assert ctypes.sizeof(R.COpts) == 16 + 24 + 40 + 8 + 8
+    assert ctypes.sizeof(R.COpts) == 16 + 24 + 40 + 8 + 8 + 8
     assert ctypes.sizeof(R.CGridDesc) == 16 + 48 + 8 + 32 + 8 + 8 + 32
     assert ctypes.sizeof(R.CStats) == 104
     pairs = {"raptor_camera": R.CCamera, "raptor_opts": R.COpts, "raptor_grid_desc": R.CGridDesc,

@@ -189,6 +189,34 @@ def test_tau_cutoff_full_size(R, ctx, orc, slow_set, nu_set):
     ctx.release_grid(gh)
 
 
+def test_optical_depth_aware_step_full_size(R, ctx, orc, slow_set):
+    """The optical-depth-aware step (tau_step 0.1) on the 256^2 spectrum camera, fast light, FP32,
+    at the spectrum's three lowest frequencies (1, 2 and 4.1 GHz, where the torus is opaque) with
+    the ln 1000 cut-off: its cost in steps and time, the flux change against the geometric step alone
+    (both are first-order discretisations of the same transfer integral, so they differ by less
+    than 1%), and sampled pixels against the oracle's same rule."""
+    cam, grid, nu24 = slow_set
+    nu = list(nu24[:3])
+    gh = ctx.upload_grid(grid)
+    geo = R.default_opts(transfer_prec=R.F32, tau_cutoff=math.log(1000.0))
+    lim = R.default_opts(transfer_prec=R.F32, tau_cutoff=math.log(1000.0), tau_step=0.1)
+    ctx.trace_spectrum(cam, gh, nu, lim)   # warm-up
+    i0, f0, s0 = ctx.trace_spectrum(cam, gh, nu, geo)
+    i1, f1, s1 = ctx.trace_spectrum(cam, gh, nu, lim)
+    f0, f1 = np.asarray(f0), np.asarray(f1)
+    rel = f1 / f0 - 1.0
+    print(f"[tau step full] geometric {s0.kernel_ms:.2f} ms {s0.ray_steps} steps; tau_step 0.1 {s1.kernel_ms:.2f} ms "
+          f"{s1.ray_steps} steps, {s1.n_opaque} opaque rays; dF/F per frequency "
+          f"{' '.join(f'{x:+.2e}' for x in rel)}",
+          flush=True)
+    assert s1.ray_steps > s0.ray_steps and s1.n_maxstep == 0 and np.abs(rel).max() < 1e-2
+    pix = sample_pixels(cam, 10, seed=S.S0 + 960)
+    worst = sampled_errors(orc, cam, grid, lim, nu, i1, pix)
+    print(f"[tau step full] sampled worst rel err {worst:.3e}", flush=True)
+    assert worst <= TOL
+    ctx.release_grid(gh)
+
+
 def test_light_curve_full_size(R, ctx, orc, slow_set):
     """A light curve of 32 slow-light frames of the 256^2 camera (t_frame stepping 10 M through
     the 64-snapshot stack) at the 4 VLBI frequencies, traced as one batch: throughput, frames
