@@ -10,7 +10,10 @@ memory before timing starts and outputs stay in device memory.
 Two forms run on the same GPU: the plain method (exact thermal-synchrotron closure) gives the
 headline value; the learned closure (network trained on the device by the library's own
 kernels before timing) is reported beside it with its total-flux error against the plain form.
-Prints one JSON line.
+Beside them, each with its own roofline: the spectrum camera (256^2, 24 frequencies, fast and
+slow light over 64 snapshots) and the uneven batch (256 images of 64^2..512^2 at four
+frequencies, autotuned plan, graph replay, exact and learned closure).  The CPU oracle is timed
+on a bounded sample on all host cores and on one.  Prints one JSON line.
 """
 import argparse
 import json
@@ -25,19 +28,24 @@ sys.path.insert(0, ROOT)
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 
 
-def cpu_baseline(sets, opts_gpu, budget_s=15.0):
-    """The oracle on this host's cores over a bounded, strided pixel sample of the same
-    workload (chunks of 64 rays per image until the time budget is spent): ray-steps per
-    second."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_sample(sets, oo, threads, budget_s):
+    """The oracle over a bounded, strided pixel sample of the workload (chunks of 64 rays per
+    image until the time budget is spent): (ray-steps, rays, seconds)."""
     import numpy as np
     from oracle import oracle as O
     import synthetic as S
-    from tests.gpu_common import oracle_opts
-    oo = oracle_opts(O, opts_gpu)
-    threads = len(os.sched_getaffinity(0))
-    env_threads = os.environ.get("OMP_NUM_THREADS")
-    if env_threads and env_threads.isdigit():
-        threads = min(threads, int(env_threads))
     handles = {id(g): O.GridHandle(g) for _, g in sets}
     steps = 0
     rays = 0
@@ -50,10 +58,129 @@ def cpu_baseline(sets, opts_gpu, budget_s=15.0):
             steps += int(st[:, 1].sum())
             rays += pix.size
         chunk += 1
-    dt = time.perf_counter() - t0
+    return steps, rays, time.perf_counter() - t0
+
+
+def cpu_baseline(sets, opts_gpu, budget_s=15.0, budget_1core_s=8.0):
+    """The oracle on this host's cores, then on one core, over bounded strided pixel samples of
+    the same workload: ray-steps per second and the equivalent 512^2 images per second."""
+    from oracle import oracle as O
+    from tests.gpu_common import oracle_opts
+    oo = oracle_opts(O, opts_gpu)
+    threads = len(os.sched_getaffinity(0))
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    if env_threads and env_threads.isdigit():
+        threads = min(threads, int(env_threads))
+    steps, rays, dt = oracle_sample(sets, oo, threads, budget_s)
+    steps1, rays1, dt1 = oracle_sample(sets, oo, 1, budget_1core_s)
     return {"value": steps / dt, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{rays} rays ({rays // len(sets)} per image, strided over the 9 images of the "
-                      f"workload), {steps} ray-steps in {dt:.1f} s, FP64, 230 GHz"}
+                      f"workload), {steps} ray-steps in {dt:.1f} s, FP64, 230 GHz",
+            "cpu_model": cpu_model(), "rays_per_s": rays / dt, "images_512_per_s": rays / dt / (512 * 512),
+            "one_core": {"value": steps1 / dt1, "unit": "ray-steps/s", "cores": 1,
+                         "rays_per_s": rays1 / dt1, "images_512_per_s": rays1 / dt1 / (512 * 512),
+                         "sample": f"{rays1} rays, {steps1} ray-steps in {dt1:.1f} s"}}
+
+
+def roofline_of(R, st, kernel_ms, fp64_transfer, n_nu):
+    """FP64 vector roofline of a trace launch from its counted work (ray-steps and samples)."""
+    w = R.work_per_unit()
+    fp64 = st["ray_steps"] * w["step_flops"] + st["samples"] * w["sample_flops"]
+    if fp64_transfer:
+        fp64 += st["samples"] * n_nu * w["freq_flops"]
+    achieved = fp64 / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "kernel": "trace_kernel (fused RK4 geodesic + transfer)"}
+
+
+def time_spectrum(ctx, R, cam, gh, nu, opts, images, flux, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        ctx.trace_spectrum(cam, gh, nu, opts, images=images, flux=flux)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(ctx.trace_spectrum(cam, gh, nu, opts, images=images, flux=flux)[2])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"ms": dt * 1e3 / steps, "ray_steps": sum(s.ray_steps for s in stats) / steps,
+            "samples": sum(s.samples for s in stats) / steps,
+            "kernel_ms": sum(s.kernel_ms for s in stats) / steps}
+
+
+def spectrum_section(args, R, S, ctx, prec):
+    """The spectrum camera: 256^2 pixels, a = 0.9375, i = 60 deg, 24 log-spaced frequencies
+    1e9..1e16 Hz on shared geodesics; fast light (the snapshot at the frame time) and slow light
+    (64 modulated float32 256^2 snapshots interpolated along each ray); graph launch."""
+    import torch
+    cam, grid, nu = S.slow_light_set()
+    gh = ctx.upload_grid(grid)
+    images = torch.empty(len(nu) * cam.nx * cam.ny, dtype=torch.float64, device="cuda")
+    flux = torch.empty(len(nu), dtype=torch.float64, device="cuda")
+    out = {"config": {"workload": "spectrum camera 256x256, a 0.9375, i 60 deg, 24 frequencies 1e9..1e16 Hz, "
+                                  "64 float32 256^2 snapshots (m=1..4 modulation, amplitude 0.2)",
+                      "n_nu": len(nu)}}
+    for name, slow in (("fast_light", 0), ("slow_light", 1)):
+        opts = R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, slow_light=slow)
+        r = time_spectrum(ctx, R, cam, gh, nu, opts, images, flux, args.steps, args.warmup)
+        out[name] = {"ms_per_step": r["ms"], "kernel_ms": r["kernel_ms"],
+                     "value": r["ray_steps"] / (r["ms"] * 1e-3), "unit": "ray-steps/s",
+                     "spectra_per_s": 1e3 / r["ms"], "ray_steps_per_step": r["ray_steps"],
+                     "samples_per_step": r["samples"],
+                     "roofline": roofline_of(R, r, r["kernel_ms"], prec == R.F64, len(nu))}
+    ctx.release_grid(gh)
+    return out
+
+
+def uneven_batch_section(args, R, S, ctx, prec):
+    """The uneven batch: 256 images of 64^2..512^2 (seeded), spin U(-0.99, 0.99), inclination
+    U(5, 85) deg, the four VLBI frequencies, one shared float32 256^2 grid; the launch plan chosen
+    by the library's autotuner on this batch, then graph replay; exact closure and, when the
+    network is trained, the learned closure with its flux error against the exact one."""
+    import numpy as np
+    import torch
+    cams = S.batch_jobs()
+    grid = S.make_grid(256, 256, a_gen=0.9375, dtype=np.float32)
+    gh = ctx.upload_grid(grid)
+    grids = [gh] * len(cams)
+    nu = S.NU_VLBI
+    n_pix = sum(c.nx * c.ny for c in cams)
+    images = torch.empty(n_pix * len(nu), dtype=torch.float64, device="cuda")
+    flux = torch.empty((len(cams), len(nu)), dtype=torch.float64, device="cuda")
+    out = {"config": {"workload": "256 images (res uniform over {64,128,256,512}^2, a U(-0.99,0.99), "
+                                  "i U(5,85) deg), 22/43/86/230 GHz, shared float32 256^2 grid, "
+                                  "autotuned plan, graph launch",
+                      "images_per_step": len(cams), "rays_per_step": n_pix,
+                      "images_512_equiv_per_step": n_pix / (512 * 512)}}
+    forms = [("exact", R.CLOSURE_EXACT)]
+    if args.mlp_ready:
+        forms.append(("mlp", R.CLOSURE_MLP))
+    fluxes = {}
+    for name, cl in forms:
+        tune = R.default_opts(transfer_prec=prec, closure=cl)
+        t0 = time.perf_counter()
+        plan, tuned_ms = R.autotune_batch(ctx, cams, grids, nu, tune, reps=1)
+        tune_s = time.perf_counter() - t0
+        opts = R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, closure=cl)
+        r = time_form(ctx, R, cams, grids, nu, opts, images, flux, args.steps, args.warmup)
+        fluxes[name] = r["flux"]
+        out[name] = {"ms_per_step": r["ms"], "kernel_ms": r["kernel_ms"],
+                     "value": r["ray_steps"] / (r["ms"] * 1e-3), "unit": "ray-steps/s",
+                     "images_per_s": len(cams) / (r["ms"] * 1e-3),
+                     "images_512_per_s": n_pix / (512 * 512) / (r["ms"] * 1e-3),
+                     "ray_steps_per_step": r["ray_steps"], "samples_per_step": r["samples"],
+                     "plan": plan.as_dict(), "autotune_s": tune_s,
+                     "roofline": roofline_of(R, r, r["kernel_ms"], prec == R.F64, len(nu))}
+        if name == "mlp":
+            out[name]["exact_fallback_fraction"] = r["fallback"] / max(r["samples"] * len(nu), 1.0)
+            out[name]["dropped_below_float_fraction"] = r["dropped"] / max(r["samples"] * len(nu), 1.0)
+    if "mlp" in fluxes:
+        rel = fluxes["mlp"] / fluxes["exact"] - 1.0
+        out["mlp"]["max_abs_flux_rel_err"] = float(np.abs(rel).max())
+    ctx.release_grid(gh)
+    return out
 
 
 def time_form(ctx, R, cams, grids, nu, opts, images, flux, steps, warmup):
@@ -75,6 +202,7 @@ def time_form(ctx, R, cams, grids, nu, opts, images, flux, steps, warmup):
             "ray_steps": sum(s.ray_steps for s in stats) / steps,
             "samples": sum(s.samples for s in stats) / steps,
             "fallback": sum(s.n_mlp_fallback for s in stats) / steps,
+            "dropped": sum(s.n_mlp_dropped for s in stats) / steps,
             "kernel_ms": sum(s.kernel_ms for s in stats) / steps,
             "kernel_ms_median": statistics.median(s.kernel_ms for s in stats),
             "flux": flux.detach().cpu().numpy().ravel().copy()}
@@ -121,6 +249,8 @@ def main():
     ap.add_argument("--mlp-epochs", type=int, default=0,
                     help="training epochs of the network (0: the library default); fewer only for profiling the "
                          "learned-closure kernel, whose cost does not depend on the weights")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the spectrum camera and the uneven 256-image batch")
     ap.add_argument("--spectrum-slow-light", action="store_true",
                     help="only time the 256^2 x 24-frequency slow-light spectrum (64 snapshots, 64 MiB of grids): "
                          "the workload whose grid gathers can reach HBM, for the memory counters")
@@ -204,6 +334,7 @@ def main():
                      "kernel": "trace_kernel (fused RK4 geodesic + transfer)",
                      "flops_per_ray_step": w["step_flops"], "flops_per_sample": w["sample_flops"]},
     }
+    args.mlp_ready = False
     if not args.no_mlp:
         R.mlp_init(ctx)
         cfg = R.mlp_default_cfg()
@@ -220,9 +351,14 @@ def main():
                       "max_abs_flux_rel_err": float(np.abs(rel).max()),
                       "flux_rel_err_per_image": [float(x) for x in rel],
                       "exact_fallback_fraction": mlp["fallback"] / max(mlp["samples"], 1.0),
+                      "dropped_below_float_fraction": mlp["dropped"] / max(mlp["samples"], 1.0),
                       "form": "split BF16 MFMA, FP32 accumulate",
                       "training": {"steps": rep.steps, "train_ms": rep.train_ms,
                                    "val_rms_ln_j": rep.val_rms[0], "val_rms_ln_alpha": rep.val_rms[1]}}
+        args.mlp_ready = True
+    if not args.no_extra:
+        out["spectrum"] = spectrum_section(args, R, S, ctx, prec)
+        out["uneven_batch"] = uneven_batch_section(args, R, S, ctx, prec)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sets, R.default_opts(transfer_prec=prec))
     print(json.dumps(out), flush=True)

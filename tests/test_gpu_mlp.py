@@ -266,3 +266,37 @@ def test_trained_network_vlbi_and_slow_light_against_oracle_exact(R, ctx, orc):
               f"fallback {sm.n_mlp_fallback}/{sm.samples * len(nu)} dropped {sm.n_mlp_dropped}", flush=True)
         worst_o, worst_g = max(worst_o, eo.max()), max(worst_g, eg.max())
     assert worst_o <= 1e-3 and worst_g <= 1e-3
+
+
+def test_trained_network_uneven_batch_autotuned_graph(R, ctx):
+    """The uneven batch (256 images of 64^2..512^2, four VLBI frequencies) with the trained
+    network, in its timed form: autotuned plan for the learned closure, graph-captured launch
+    equal bit for bit to the direct launch, and every (image, frequency) flux within 1e-3 of the
+    exact closure's."""
+    import torch
+    if not getattr(ctx, "_trained", False):
+        R.mlp_init(ctx)
+        R.mlp_train(ctx)
+        ctx._trained = True
+    cams = S.batch_jobs()
+    gh = ctx.upload_grid(S.make_grid(256, 256, a_gen=0.9375, dtype=np.float32))
+    grids = [gh] * len(cams)
+    nu = S.NU_VLBI
+    mlp = R.default_opts(transfer_prec=R.F32, closure=R.CLOSURE_MLP)
+    plan, ms = R.autotune_batch(ctx, cams, grids, nu, mlp, reps=1)
+    ex_i, ex_f, ex_st = ctx.trace_batch(cams, grids, nu, R.default_opts(transfer_prec=R.F32))
+    ref_i, ref_f, ref_st = ctx.trace_batch(cams, grids, nu, mlp)
+    n = sum(c.nx * c.ny for c in cams) * len(nu)
+    img = torch.empty(n, dtype=torch.float64, device="cuda")
+    flux = torch.empty((len(cams), len(nu)), dtype=torch.float64, device="cuda")
+    _, _, st = ctx.trace_batch(cams, grids, nu, R.default_opts(transfer_prec=R.F32, closure=R.CLOSURE_MLP,
+                                                               mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH),
+                               images=img, flux=flux)
+    torch.cuda.synchronize()
+    assert np.array_equal(img.cpu().numpy(), ref_i) and np.array_equal(flux.cpu().numpy(), ref_f)
+    rel = np.abs(np.asarray(ref_f) / np.asarray(ex_f) - 1.0)
+    print(f"[mlp uneven batch] plan {plan.as_dict()} learned {st.kernel_ms:.1f} ms exact {ex_st.kernel_ms:.1f} ms; "
+          f"max |dF/F| {rel.max():.3e}; fallback {ref_st.n_mlp_fallback / (ref_st.samples * len(nu)):.4f} "
+          f"dropped {ref_st.n_mlp_dropped / (ref_st.samples * len(nu)):.4f}", flush=True)
+    assert rel.max() <= 1e-3
+    ctx.release_grid(gh)

@@ -100,6 +100,33 @@ def test_uneven_batch_full_size(R, ctx, orc):
     ctx.release_grid(gh)
 
 
+def test_uneven_batch_autotuned_graph_replay(R, ctx):
+    """The uneven batch in its timed form: the autotuner picks a plan on the 256 images (exact
+    closure, FP32 transfer), and the graph-captured launch replayed twice under that plan gives
+    bitwise the images and fluxes of the direct launch under the same plan."""
+    import torch
+    cams = S.batch_jobs()
+    grid = S.make_grid(256, 256, a_gen=0.9375, dtype=np.float32)
+    gh = ctx.upload_grid(grid)
+    grids = [gh] * len(cams)
+    nu = S.NU_VLBI
+    plan, ms = R.autotune_batch(ctx, cams, grids, nu, R.default_opts(transfer_prec=R.F32), reps=1)
+    print(f"[uneven batch autotune] plan {plan.as_dict()} best kernel {ms:.1f} ms", flush=True)
+    n = sum(c.nx * c.ny for c in cams) * len(nu)
+    ref_i, ref_f, ref_st = ctx.trace_batch(cams, grids, nu, R.default_opts(transfer_prec=R.F32))
+    img = torch.empty(n, dtype=torch.float64, device="cuda")
+    flux = torch.empty((len(cams), len(nu)), dtype=torch.float64, device="cuda")
+    graph = R.default_opts(transfer_prec=R.F32, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH)
+    for rep in range(2):
+        _, _, st = ctx.trace_batch(cams, grids, nu, graph, images=img, flux=flux)
+        torch.cuda.synchronize()
+        assert np.array_equal(img.cpu().numpy(), ref_i) and np.array_equal(flux.cpu().numpy(), ref_f), rep
+        assert st.ray_steps == ref_st.ray_steps
+    print(f"[uneven batch graph] {st.kernel_ms:.1f} ms, {st.ray_steps / st.kernel_ms * 1e3:.3e} ray-steps/s",
+          flush=True)
+    ctx.release_grid(gh)
+
+
 def test_light_curve_batch(R, ctx, orc):
     """Light curve (Sec. 5): 16 slow-light frames of one camera, t_frame stepping by 10 M across
     the 64-snapshot stack, traced as one batch at 4 VLBI frequencies.  Each frame's flux equals
