@@ -93,8 +93,7 @@ struct raptor_grid {
     DevGrid d{};
     double mass_unit_g = 0.0;   // code-unit grids: the model's mass unit
     void* cells = nullptr;
-    float2* x2tab = nullptr;
-    double2* x2sc = nullptr;
+    double2* x2tab = nullptr;
     raptor_ctx* owner = nullptr;
 };
 

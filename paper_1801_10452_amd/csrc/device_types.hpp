@@ -7,10 +7,9 @@
 // {n_e, Theta_e, B, Omega}.
 struct DevGrid {
     const void* cells;
-    const float2* x2tab;       // {x2, dx2/dtheta} at x2n uniform theta nodes on [0, pi] (start values)
-    const double2* x2sc;       // {sin, cos}(2 pi x2) of the tabulated (float) x2 of each node
-    int x2n, pad;
-    double x2_inv_dth, x2_dth;
+    const double2* x2tab;      // {x2, dx2/dtheta * dtheta} at the x2n + 1 nodes theta = i pi / x2n
+    int x2n, x2_refine;        // x2_refine: the table misses 1e-12 somewhere, refine by Halley's iteration
+    double x2_inv_dth;         // x2n / pi
     int n1, n2, n_snap, is_f64;
     double lnr_in, inv_d1, r_in, r_out, hslope, a_gen, t0, dt_snap, inv_dt, mod_amp;
     double mod_cos[4], mod_sin[4];   // cos / sin of the modulation phases

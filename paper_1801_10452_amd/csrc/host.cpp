@@ -589,7 +589,6 @@ void raptor_destroy(raptor_ctx* ctx)
     for (raptor_grid* g : ctx->live) {
         if (g->cells) (void)hipFree(g->cells);
         if (g->x2tab) (void)hipFree(g->x2tab);
-        if (g->x2sc) (void)hipFree(g->x2sc);
         delete g;
     }
     ctx->jobs.release();
@@ -644,6 +643,8 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
     if (!d || !out || !d->cells) return fail(ctx, RAPTOR_E_INVALID, "desc, desc->cells and out must be non-NULL");
     if (d->n1 < 2 || d->n2 < 2 || d->n_snap < 1) return fail(ctx, RAPTOR_E_INVALID, "need n1, n2 >= 2 and n_snap >= 1");
     if (d->dtype != RAPTOR_F32 && d->dtype != RAPTOR_F64) return fail(ctx, RAPTOR_E_INVALID, "unknown grid dtype");
+    if ((double)d->n_snap * d->n2 * d->n1 >= 2147483647.0)
+        return fail(ctx, RAPTOR_E_RANGE, "a grid holds fewer than 2^31 cells");
     if (!(finite_pos(d->r_in) && std::isfinite(d->r_out) && d->r_out > d->r_in))
         return fail(ctx, RAPTOR_E_INVALID, "need 0 < r_in < r_out");
     if (!(d->hslope > 0.0 && d->hslope <= 1.0)) return fail(ctx, RAPTOR_E_INVALID, "hslope must be in (0, 1]");
@@ -672,37 +673,54 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
         delete g;
         return dev_fail(ctx, e, "uploading the grid");
     }
-    // start values of the MKS inverse on uniform theta nodes (Newton on the host): x2(theta) and
-    // dx2/dtheta at 1024 nodes (8 KiB) for the cubic Hermite start value of the chart inversion,
-    // and sin, cos of 2 pi x2 at the stored node values (16 KiB) for its first iteration
-    const int x2n = 1024;
-    std::vector<float2> x2h(x2n);
-    std::vector<double2> sch(x2n);
-    for (int i = 0; i < x2n; ++i) {
-        const double th = kPi * i / (x2n - 1);
+    // The MKS inverse x2(theta) as a cubic Hermite table on uniform theta nodes (Newton on the
+    // host), with the node count doubled from 4096 until the interpolation error, checked at three
+    // points of every interval, is at most 1e-12; where 32768 nodes do not reach it (strongly
+    // concentrated grids, hslope below ~0.2) the kernel refines the table value by Halley's
+    // iteration.
+    const double hh = 0.5 * (1.0 - d->hslope);
+    auto solve = [&](double th) {
         double x = th / kPi;
         for (int it = 0; it < 100; ++it) {
-            const double f = kPi * x + 0.5 * (1.0 - d->hslope) * std::sin(2.0 * kPi * x) - th;
-            const double fp = kPi * (1.0 + (1.0 - d->hslope) * std::cos(2.0 * kPi * x));
+            const double f = kPi * x + hh * std::sin(2.0 * kPi * x) - th;
+            const double fp = kPi * (1.0 + 2.0 * hh * std::cos(2.0 * kPi * x));
             const double xn = std::min(std::max(x - f / fp, 0.0), 1.0);
-            const bool done = std::fabs(xn - x) < 1e-15;
+            const bool done = std::fabs(xn - x) < 1e-16;
             x = xn;
             if (done) break;
         }
-        x2h[i].x = (float)x;
-        x2h[i].y = (float)(1.0 / (kPi * (1.0 + (1.0 - d->hslope) * std::cos(2.0 * kPi * x))));
-        // sin and cos of 2 pi times the stored (float) node value, for the shifted first iteration
-        const double xf = (double)x2h[i].x;
-        sch[i].x = std::sin(2.0 * kPi * xf);
-        sch[i].y = std::cos(2.0 * kPi * xf);
+        return x;
+    };
+    std::vector<double2> x2h;
+    int x2n = 4096, refine = 1;
+    for (; x2n <= 32768; x2n *= 2) {
+        const double dth = kPi / x2n;
+        x2h.assign(x2n + 1, double2{0.0, 0.0});
+        for (int i = 0; i <= x2n; ++i) {
+            const double x = solve(dth * i);
+            x2h[i].x = x;
+            x2h[i].y = dth / (kPi * (1.0 + 2.0 * hh * std::cos(2.0 * kPi * x)));   // dx2/dtheta * dtheta
+        }
+        double worst = 0.0;
+        for (int i = 0; i < x2n && worst <= 1e-12; ++i) {
+            for (double s : {0.25, 0.5, 0.75}) {
+                const double s2 = s * s, s3 = s2 * s;
+                const double v = (2.0 * s3 - 3.0 * s2 + 1.0) * x2h[i].x + (s3 - 2.0 * s2 + s) * x2h[i].y +
+                                 (-2.0 * s3 + 3.0 * s2) * x2h[i + 1].x + (s3 - s2) * x2h[i + 1].y;
+                worst = std::max(worst, std::fabs(v - solve(dth * (i + s))));
+            }
+        }
+        if (worst <= 1e-12) {
+            refine = 0;
+            break;
+        }
+        if (x2n == 32768) break;
     }
-    e = hipMalloc(&g->x2tab, x2n * sizeof(float2));
-    if (e == hipSuccess) e = hipMemcpy(g->x2tab, x2h.data(), x2n * sizeof(float2), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&g->x2sc, x2n * sizeof(double2));
-    if (e == hipSuccess) e = hipMemcpy(g->x2sc, sch.data(), x2n * sizeof(double2), hipMemcpyHostToDevice);
+    e = hipMalloc(&g->x2tab, (x2n + 1) * sizeof(double2));
+    if (e == hipSuccess)
+        e = hipMemcpy(g->x2tab, x2h.data(), (x2n + 1) * sizeof(double2), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (g->x2tab) (void)hipFree(g->x2tab);
-        if (g->x2sc) (void)hipFree(g->x2sc);
         (void)hipFree(g->cells);
         delete g;
         return dev_fail(ctx, e, "uploading the MKS table");
@@ -710,10 +728,9 @@ raptor_status raptor_grid_upload(raptor_ctx* ctx, const raptor_grid_desc* d, rap
     DevGrid& G = g->d;
     G.cells = g->cells;
     G.x2tab = g->x2tab;
-    G.x2sc = g->x2sc;
     G.x2n = x2n;
-    G.x2_inv_dth = (x2n - 1) / kPi;
-    G.x2_dth = kPi / (x2n - 1);
+    G.x2_refine = refine;
+    G.x2_inv_dth = x2n / kPi;
     G.n1 = d->n1;
     G.n2 = d->n2;
     G.n_snap = d->n_snap;
@@ -755,7 +772,6 @@ void raptor_grid_release(raptor_ctx* ctx, raptor_grid* g)
     (void)hipStreamSynchronize(ctx->stream);
     if (g->cells) (void)hipFree(g->cells);
     if (g->x2tab) (void)hipFree(g->x2tab);
-    if (g->x2sc) (void)hipFree(g->x2sc);
     ctx->live.erase(it);
     delete g;
 }
@@ -1161,14 +1177,13 @@ raptor_status raptor_work_per_unit(double* step_flops, double* step_special, dou
     if (step_flops) *step_flops = rt::g_tally.flops;
     if (step_special) *step_special = rt::g_tally.special;
 
-    // one sample, frequency-independent part: grid coordinates (7), one Newton iteration of
-    // the MKS map, bilinear interpolation, fluid frame, path length (2), 1/nu_r^3 (2), sin
-    // theta_B (2), K2 lookup (Hermite, 20)
-    const double root = pl::mks_x2(0.3, rt::val(y[2]), rt::val(y[2]) / kPi);
+    // one sample, frequency-independent part: grid coordinates (7), the MKS map's x2 from its
+    // cubic Hermite table (22: cell position 2, basis 12, combination 8; grids whose table is
+    // refined by Halley's iteration do more), bilinear interpolation, fluid frame, path length
+    // (2), 1/nu_r^3 (2), sin theta_B (2), K2 lookup (Hermite, 20)
     rt::g_tally = rt::OpTally{};
     (void)rt::log_(y[1]);
-    rt::g_tally.flops += 7 + 16;               // grid coordinates; Hermite start value from the x2 table
-    (void)pl::mks_x2(C(0.3), y[2], C(root));   // starts at the root: exactly one iteration
+    rt::g_tally.flops += 7 + 22;
     C a[4] = {1, 2, 3, 4}, b[4] = {1, 2, 3, 4}, c[4] = {1, 2, 3, 4}, d[4] = {1, 2, 3, 4}, o4[4];
     pl::bilerp4(a, b, c, d, C(0.3), C(0.6), o4);
     C nr, cb;

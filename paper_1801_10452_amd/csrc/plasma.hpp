@@ -70,27 +70,33 @@ __host__ __device__ inline void bilerp4(const T* a, const T* b, const T* c, cons
     for (int f = 0; f < 4; ++f) out[f] = u2 * (u1 * a[f] + w1 * b[f]) + w2 * (u1 * c[f] + w1 * d[f]);
 }
 
-__device__ inline void load_cell(const DevGrid& g, int s, int j, int i, double v[4])
+template <class V>
+__device__ inline void cell_values(const V& q, double v[4])
 {
-    const size_t idx = ((size_t)s * g.n2 + j) * g.n1 + i;
-    if (g.is_f64) {
-        const double4 q = reinterpret_cast<const double4*>(g.cells)[idx];
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
-        const float4 q = reinterpret_cast<const float4*>(g.cells)[idx];
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    }
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
 }
 
 // Bilinear interpolation between cell centres (clamped to the edge centres in the outer
-// half cells) of snapshot s at fractional cell coordinates computed by the caller.
+// half cells) of snapshot s at fractional cell coordinates computed by the caller.  The four
+// cells are (j0, i0), (j0, i0 + 1), (j0 + 1, i0), (j0 + 1, i0 + 1); a grid holds fewer than 2^31
+// cells (checked at upload), so their index is 32-bit.
 __device__ inline void bilinear(const DevGrid& g, int s, int i0, int j0, double w1, double w2, double out[4])
 {
+    const int idx = (s * g.n2 + j0) * g.n1 + i0;
     double a[4], b[4], c[4], d[4];
-    load_cell(g, s, j0, i0, a);
-    load_cell(g, s, j0, i0 + 1, b);
-    load_cell(g, s, j0 + 1, i0, c);
-    load_cell(g, s, j0 + 1, i0 + 1, d);
+    if (g.is_f64) {
+        const double4* p = reinterpret_cast<const double4*>(g.cells) + idx;
+        cell_values(p[0], a);
+        cell_values(p[1], b);
+        cell_values(p[g.n1], c);
+        cell_values(p[g.n1 + 1], d);
+    } else {
+        const float4* p = reinterpret_cast<const float4*>(g.cells) + idx;
+        cell_values(p[0], a);
+        cell_values(p[1], b);
+        cell_values(p[g.n1], c);
+        cell_values(p[g.n1 + 1], d);
+    }
     bilerp4(a, b, c, d, w1, w2, out);
 }
 
@@ -120,39 +126,23 @@ __device__ inline double modulation(const DevGrid& g, double r, double ph, doubl
     return 1.0 + g.mod_amp * acc;
 }
 
-// Start value of the MKS inverse: cubic Hermite interpolation in the grid's {x2, dx2/dtheta} table.
-__device__ inline double x2_start(const DevGrid& g, double th)
-{
-    double q = ::fmin(::fmax(th * g.x2_inv_dth, 0.0), (double)(g.x2n - 1) - 1e-9);
-    const int i = (int)q;
-    const double s = q - i;
-    const float2 A = g.x2tab[i], B = g.x2tab[i + 1];
-    const double s2 = s * s, s3 = s2 * s;
-    const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
-    const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
-    return h00 * A.x + h10 * A.y * g.x2_dth + h01 * B.x + h11 * B.y * g.x2_dth;
-}
-
-// x2(theta): the Hermite start value, then Halley's iteration (mks_x2).  The first iteration
-// takes sin and cos of 2 pi x from the table's values at the left node's x2 (stored as a
-// float, the table holds sin and cos of exactly that value) and the angle-addition shift by
-// 2 pi (x - x_node), |shift| <= 2 pi (node spacing in x2), instead of a full sine-cosine.
+// x2(theta), the inverse of the MKS polar map: cubic Hermite interpolation between the grid's
+// table nodes (x2 and dx2/dtheta solved by Newton's iteration on the host, uniform in theta), whose
+// node count the upload chose so that the interpolation is within 1e-12 of the root; a grid whose
+// table cannot reach that (x2_refine) takes Halley's iteration from the interpolated value to
+// convergence, with the paper's reset rule (mks_x2).
 __device__ inline double x2_of_theta(const DevGrid& g, double th)
 {
-    double q = ::fmin(::fmax(th * g.x2_inv_dth, 0.0), (double)(g.x2n - 1) - 1e-9);
+    const double q = ::fmin(::fmax(th * g.x2_inv_dth, 0.0), (double)g.x2n - 1e-9);
     const int i = (int)q;
     const double s = q - i;
-    const float2 A = g.x2tab[i], B = g.x2tab[i + 1];
-    const double2 SC = g.x2sc[i];
+    const double2 A = g.x2tab[i], B = g.x2tab[i + 1];
     const double s2 = s * s, s3 = s2 * s;
     const double h00 = 2.0 * s3 - 3.0 * s2 + 1.0, h10 = s3 - 2.0 * s2 + s;
     const double h01 = -2.0 * s3 + 3.0 * s2, h11 = s3 - s2;
-    const double x0 = h00 * A.x + h10 * A.y * g.x2_dth + h01 * B.x + h11 * B.y * g.x2_dth;
-    double sn, cs;
-    rk::sincos_add(2.0 * PI_D * x0, 2.0 * PI_D * (x0 - (double)A.x), SC.x, SC.y, &sn, &cs);
-    const double x1 = mks_halley(g.hslope, th, x0, sn, cs);
-    if (::fabs(x1 - x0) < 1e-6) return x1;
-    return mks_x2(g.hslope, th, x1);
+    const double x0 = h00 * A.x + h10 * A.y + h01 * B.x + h11 * B.y;
+    if (!g.x2_refine) return x0;
+    return mks_x2(g.hslope, th, x0);
 }
 
 __device__ inline bool in_plasma(const DevGrid& g, double r) { return r >= g.r_in && r <= g.r_out; }

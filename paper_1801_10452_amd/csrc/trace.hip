@@ -96,7 +96,7 @@ struct Transfer<float> {
         inv_the = rt::rcpf_nr(the);
         nr = nr_;
         ds = (float)dsv;
-        inr3 = (float)rt::rcp_nr(nr_ * nr_ * nr_);
+        inr3 = rt::rcpf_nr((float)(nr_ * nr_ * nr_));
         const double s2 = 1.0 - cosb * cosb;
         const double sb = s2 > 0.0 ? s2 * rt::rsqrt_nr(s2) : 0.0;
         emits = (fl[0] > 0.0 && fl[1] > 0.0 && fl[2] > 0.0 && sb > 0.0);
@@ -133,12 +133,12 @@ struct Transfer<float> {
         const float nuf = (float)(nu_obs * nr);
         const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
         const float q3 = q * q * q;                               // 2 h nu^3 / c^2
-        const float em1 = ::expm1f((float)pl::H_OVER_MEC2 * nuf * inv_the);
+        const float em1 = rt::expm1_f((float)pl::H_OVER_MEC2 * nuf * inv_the);
         const float S = q3 * rt::rcpf_nr(em1);                    // B_nu
         const float dtm = jm * em1 * rt::rcpf_nr(q3) * ds;        // dtau = dtm 2^-n
         dtau = (double)dtm * scale;
         if (dtau > 1e-8) {
-            A = (double)(S * -::expm1f(-(float)dtau) * inr3);
+            A = (double)(S * -rt::expm1_f(-(float)dtau) * inr3);
         } else {
             // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): S dtau = j ds to float precision
             A = (double)(jm * ds * inr3) * scale;
@@ -252,13 +252,13 @@ __device__ inline void mlp_contribution_f32(const Transfer<float>& tr, float y0,
     const float ej = __expf(y0 * mlp::SIGMA_J + mlp::MU_J), ea = __expf(y1 * mlp::SIGMA_A + mlp::MU_A);
     const float nucf = (float)nuc;
     const float yy = (float)pl::H_OVER_MEC2 * (float)(nu_obs * tr.nr) * tr.inv_the;
-    const float planck = (yy > 1e-4f) ? ::expm1f(yy) * rt::rcpf_nr(yy) : 1.0f + 0.5f * yy;   // B_RJ / B_nu
+    const float planck = (yy > 1e-4f) ? rt::expm1_f(yy) * rt::rcpf_nr(yy) : 1.0f + 0.5f * yy;   // B_RJ / B_nu
     const float jm = tr.ne * nucf * (float)pl::J_PREF * ej * em;                                 // j = jm 2^-n
     const float am = tr.ne * (float)(pl::J_PREF / (2.0 * pl::ME_CGS)) * rt::rcpf_nr(nucf) * ea * em * planck;
     const float dtm = am * tr.ds;                                                                // dtau = dtm 2^-n
     dtau = (double)dtm * scale;
     if (dtau > 1e-8) {
-        A = (double)(jm * rt::rcpf_nr(am) * -::expm1f(-(float)dtau) * tr.inr3);
+        A = (double)(jm * rt::rcpf_nr(am) * -rt::expm1_f(-(float)dtau) * tr.inr3);
     } else {
         // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): S dtau = j ds to float precision
         A = (double)(jm * tr.ds * tr.inr3) * scale;
