@@ -81,11 +81,11 @@ __global__ void exact_kernel(K2Table k2, long long n, const float* raw, float* o
 }
 
 // ------------------------------------------------------------------------------------------
-// Training: one wave (one work-group) per 64 samples.
+// Training: one work-group of four waves per 64 samples.
 // LDS: Z[4][64][64] pre-activations (BF16, [sample][feature]), two dZ buffers [64][64] (BF16),
-// X[64][16] inputs (BF16).
+// X[64][16] inputs (BF16), 8 loss floats.
 // ------------------------------------------------------------------------------------------
-constexpr int TR_LDS = (4 * 64 * 64 + 2 * 64 * 64 + 64 * 16) * 2;
+constexpr int TR_LDS = (4 * 64 * 64 + 2 * 64 * 64 + 64 * 16) * 2 + 8 * 4;
 
 __device__ inline void lds_sync()
 {
@@ -120,34 +120,35 @@ __device__ inline bf16x4 frag_samples(const unsigned short* M, int rs, int f0, i
     return pack4(v[0], v[1], v[2], v[3]);
 }
 
-// dW[out][in] (+)= sum_s dZ[s][out] H[s][in] over the wave's 64 samples; writes the wave partial.
+// dW[out][in] = sum_s dZ[s][out] H[s][in] over the work-group's 64 samples; writes the partial.
 // dZ: [64][64] BF16 (first out_tiles*16 features used); H: [64][rs] BF16 (pre-activations if
 // ACT, raw inputs otherwise); db[out] = sum_s dZ[s][out].
+// The four waves of a work-group share the (out tile, in tile) pairs, pair i on wave i mod 4, and
+// the bias entries, out = 16 wave + (lane < 16 ? lane : -): each entry is computed by one wave,
+// with the same instruction sequence whichever wave it is.
 template <bool ACT>
 __device__ inline void weight_grad(const unsigned short* dZ, const unsigned short* H, int rs, int out_tiles,
-                                   int in_tiles, int out_dim, int in_dim, float* gW, float* gb, int lane)
+                                   int in_tiles, int out_dim, int in_dim, float* gW, float* gb, int wave, int lane)
 {
     const int g4 = 4 * (lane >> 4), n = lane & 15;
-    for (int mt = 0; mt < out_tiles; ++mt) {
-        bf16x4 a[4];
+    for (int pr = wave; pr < out_tiles * in_tiles; pr += 4) {
+        const int mt = pr / in_tiles, nt = pr % in_tiles;
+        f32x4 acc = f32x4{0, 0, 0, 0};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) a[kt] = frag_samples<false>(dZ, 64, 16 * mt, kt, lane);
-        for (int nt = 0; nt < in_tiles; ++nt) {
-            f32x4 acc = f32x4{0, 0, 0, 0};
+        for (int kt = 0; kt < 4; ++kt)
+            acc = mfma(frag_samples<false>(dZ, 64, 16 * mt, kt, lane), frag_samples<ACT>(H, rs, 16 * nt, kt, lane), acc);
+        const int in = 16 * nt + n;
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) acc = mfma(a[kt], frag_samples<ACT>(H, rs, 16 * nt, kt, lane), acc);
-            const int in = 16 * nt + n;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int out = 16 * mt + g4 + j;
-                if (out < out_dim && in < in_dim) gW[out * in_dim + in] = acc[j];
-            }
+        for (int j = 0; j < 4; ++j) {
+            const int out = 16 * mt + g4 + j;
+            if (out < out_dim && in < in_dim) gW[out * in_dim + in] = acc[j];
         }
     }
-    if (lane < out_dim) {
+    const int out = 16 * wave + lane;
+    if (lane < 16 && out < out_dim) {
         float s = 0.0f;
-        for (int smp = 0; smp < 64; ++smp) s += bf2f(dZ[smp * 64 + lane]);
-        gb[lane] = s;
+        for (int smp = 0; smp < 64; ++smp) s += bf2f(dZ[smp * 64 + out]);
+        gb[out] = s;
     }
 }
 
@@ -168,24 +169,87 @@ __device__ inline void backprop_block(const unsigned short* WT, int out_pad, int
     }
 }
 
+// The work-group's copy of the BF16 weights in LDS: W hi and lo [out_pad][in_pad] and WT
+// [in_pad][out_pad] of the five layers, each row padded by four BF16 so that the sixteen rows a
+// fragment read touches start in different banks.  Offsets and strides in BF16 units.
+namespace tw {
+constexpr int out_pad(int L) { return L == 4 ? 16 : 64; }
+constexpr int in_pad(int L) { return L == 0 ? 16 : 64; }
+constexpr int w_stride(int L) { return in_pad(L) + 4; }
+constexpr int t_stride(int L) { return out_pad(L) + 4; }
+constexpr int w_size(int L) { return out_pad(L) * w_stride(L); }
+constexpr int t_size(int L) { return in_pad(L) * t_stride(L); }
+constexpr int w_off(int L) { return L == 0 ? 0 : w_off(L - 1) + w_size(L - 1); }
+constexpr int t_off(int L) { return L == 0 ? 0 : t_off(L - 1) + t_size(L - 1); }
+constexpr int COPY = w_off(5);   // BF16 per copy (W, W lo and WT have the same size)
+constexpr int BYTES = 3 * COPY * 2;
+static_assert(COPY == t_off(5), "W and WT copies of the same size");
+}  // namespace tw
+constexpr int PW_OF[5] = {PW1, PW2, PW3, PW4, PW5};
+
+// Copy the padded global layouts into the LDS layout, eight bytes per move.
+__device__ inline void stage_train_weights(const Net& net, unsigned short* dst)
+{
+    for (int L = 0; L < 5; ++L) {
+        const int wr = tw::out_pad(L), wc = tw::in_pad(L) / 4;   // W rows, 8-byte chunks per row
+        for (int i = threadIdx.x; i < wr * wc; i += blockDim.x) {
+            const int r = i / wc, c = 4 * (i % wc);
+            const int d = tw::w_off(L) + r * tw::w_stride(L) + c;
+            const int sidx = PW_OF[L] + r * tw::in_pad(L) + c;
+            *reinterpret_cast<bf16x4*>(dst + d) = *reinterpret_cast<const bf16x4*>(net.W + sidx);
+            *reinterpret_cast<bf16x4*>(dst + tw::COPY + d) = *reinterpret_cast<const bf16x4*>(net.Wlo + sidx);
+        }
+        const int tr = tw::in_pad(L), tc = tw::out_pad(L) / 4;
+        for (int i = threadIdx.x; i < tr * tc; i += blockDim.x) {
+            const int r = i / tc, c = 4 * (i % tc);
+            *reinterpret_cast<bf16x4*>(dst + 2 * tw::COPY + tw::t_off(L) + r * tw::t_stride(L) + c) =
+                *reinterpret_cast<const bf16x4*>(net.WT + PW_OF[L] + r * tw::out_pad(L) + c);
+        }
+    }
+}
+
+// Weight source of forward_block reading that LDS copy (biases from the FP32 parameters).
+template <bool SPLIT>
+struct LdsTrainWeights {
+    const unsigned short* lw;
+    const float* P;
+    __device__ inline Split w(int layer, int mt, int kt, int lane) const
+    {
+        return frag_w<SPLIT>(lw + tw::w_off(layer), lw + tw::COPY + tw::w_off(layer),
+                             tw::w_stride(layer), 16 * mt, 16 * kt, lane);
+    }
+    __device__ inline const float* bias(int layer) const { return P + hidden_bias_off(layer); }
+    __device__ inline float out_bias(int o) const { return P[OFF_B5 + o]; }
+};
+
 // mode 0: gradient of the mean squared error against T (standardised targets), loss sums to
-// loss[wave]; mode 1: gradient of sum dY . y for given dY.
-__global__ void __launch_bounds__(64) train_kernel(Net net, const float* X, const float* T, const float* DY, long long base,
-                                                   long long n, int mode, float inv_batch, float* partial, float* loss)
+// loss[2 block], loss[2 block + 1]; mode 1: gradient of sum dY . y for given dY.
+// A work-group of four waves takes 64 samples: in the forward pass and in every backward step
+// (dZ through the transposed weights) wave w handles the 16 samples of column block w; the
+// weight gradients, which sum over all 64 samples, are shared out by output tiles (see
+// weight_grad).  Every result is computed by one wave with the instruction sequence a single
+// wave would use for it, so the partial gradient does not depend on the wave count.
+__global__ void __launch_bounds__(256) train_kernel(Net net, const float* X, const float* T, const float* DY, long long base,
+                                                    long long n, int mode, float inv_batch, float* partial, float* loss)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned short* Z = reinterpret_cast<unsigned short*>(lds);   // [4][64][64]
     unsigned short* dA = Z + 4 * 64 * 64;                          // [64][64]
     unsigned short* dB = dA + 64 * 64;                              // [64][64]
     unsigned short* Xs = dB + 64 * 64;                              // [64][16]
-    const int lane = threadIdx.x;
+    float* lred = reinterpret_cast<float*>(Xs + 64 * 16);           // [4][2] per-wave loss sums
+    unsigned short* lw = reinterpret_cast<unsigned short*>(lds + TR_LDS);   // tw layout
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    stage_train_weights(net, lw);
+    lds_sync();
     const int g4 = 4 * (lane >> 4), nl = lane & 15;
     const long long s0 = base + 64ll * blockIdx.x;
     float* gw = partial + (size_t)blockIdx.x * N_PARAMS;
     float l0 = 0.0f, l1 = 0.0f;
 
-    // ---- forward of the four column blocks; keep pre-activations, form dY = dZ5
-    for (int cb = 0; cb < 4; ++cb) {
+    // ---- forward of this wave's column block; keep pre-activations, form dY = dZ5
+    {
+        const int cb = wave;
         const int s = 16 * cb + nl;
         const long long gs = s0 + s;
         const bool valid = gs < n;
@@ -200,7 +264,7 @@ __global__ void __launch_bounds__(64) train_kernel(Net net, const float* X, cons
         bx.lo = (lane < 16) ? split4(x0, x1, x2, 0.0f).lo : bf16x4{0, 0, 0, 0};
         store4(Xs + s * 16 + g4, lane < 16 ? x0 : 0.0f, lane < 16 ? x1 : 0.0f, lane < 16 ? x2 : 0.0f, 0.0f);
         f32x4 z[16];
-        const f32x4 o = forward_block<true>(net, bx, lane, z);
+        const f32x4 o = forward_block<true>(LdsTrainWeights<true>{lw, net.P}, bx, lane, z);
 #pragma unroll
         for (int L = 0; L < 4; ++L)
 #pragma unroll
@@ -212,8 +276,8 @@ __global__ void __launch_bounds__(64) train_kernel(Net net, const float* X, cons
         if (lane < 16 && valid) {
             if (mode == 0) {
                 const float e0 = o.x - T[2 * gs], e1 = o.y - T[2 * gs + 1];
-                l0 += e0 * e0;
-                l1 += e1 * e1;
+                l0 = e0 * e0;
+                l1 = e1 * e1;
                 d0 = e0 * inv_batch;
                 d1 = e1 * inv_batch;
             } else {
@@ -225,32 +289,40 @@ __global__ void __launch_bounds__(64) train_kernel(Net net, const float* X, cons
     }
     lds_sync();
     // ---- layer 5 (64 -> 2)
-    weight_grad<true>(dA, Z + 3 * 4096, 64, 1, 4, 2, 64, gw + OFF_W5, gw + OFF_B5, lane);
-    for (int cb = 0; cb < 4; ++cb) backprop_block(net.WT + PW5, 16, 1, dA, Z + 3 * 4096, dB, cb, lane);
+    weight_grad<true>(dA, Z + 3 * 4096, 64, 1, 4, 2, 64, gw + OFF_W5, gw + OFF_B5, wave, lane);
+    const unsigned short* lwt = lw + 2 * tw::COPY;
+    backprop_block(lwt + tw::t_off(4), tw::t_stride(4), 1, dA, Z + 3 * 4096, dB, wave, lane);
     lds_sync();
     // ---- layers 4, 3, 2
     unsigned short* cur = dB;
     unsigned short* nxt = dA;
-    const int offw[3] = {OFF_W4, OFF_W3, OFF_W2}, offb[3] = {OFF_B4, OFF_B3, OFF_B2}, pw[3] = {PW4, PW3, PW2};
+    const int offw[3] = {OFF_W4, OFF_W3, OFF_W2}, offb[3] = {OFF_B4, OFF_B3, OFF_B2};
     for (int i = 0; i < 3; ++i) {
         const int L = 3 - i;   // pre-activation index of this layer's input: Z[L - 1]
-        weight_grad<true>(cur, Z + (L - 1) * 4096, 64, 4, 4, 64, 64, gw + offw[i], gw + offb[i], lane);
-        for (int cb = 0; cb < 4; ++cb) backprop_block(net.WT + pw[i], 64, 4, cur, Z + (L - 1) * 4096, nxt, cb, lane);
+        weight_grad<true>(cur, Z + (L - 1) * 4096, 64, 4, 4, 64, 64, gw + offw[i], gw + offb[i], wave, lane);
+        backprop_block(lwt + tw::t_off(3 - i), tw::t_stride(3 - i), 4, cur, Z + (L - 1) * 4096, nxt,
+                       wave, lane);
         lds_sync();
         unsigned short* t = cur;
         cur = nxt;
         nxt = t;
     }
     // ---- layer 1 (3 -> 64)
-    weight_grad<false>(cur, Xs, 16, 4, 1, 64, 3, gw + OFF_W1, gw + OFF_B1, lane);
+    weight_grad<false>(cur, Xs, 16, 4, 1, 64, 3, gw + OFF_W1, gw + OFF_B1, wave, lane);
     if (mode == 0) {
+        // per-wave sums in a fixed tree, then the four waves in order
         for (int o = 32; o > 0; o >>= 1) {
             l0 += __shfl_xor(l0, o, 64);
             l1 += __shfl_xor(l1, o, 64);
         }
         if (lane == 0) {
-            loss[2 * blockIdx.x] = l0;
-            loss[2 * blockIdx.x + 1] = l1;
+            lred[2 * wave] = l0;
+            lred[2 * wave + 1] = l1;
+        }
+        lds_sync();
+        if (threadIdx.x == 0) {
+            loss[2 * blockIdx.x] = ((lred[0] + lred[2]) + lred[4]) + lred[6];
+            loss[2 * blockIdx.x + 1] = ((lred[1] + lred[3]) + lred[5]) + lred[7];
         }
     }
 }
@@ -271,16 +343,34 @@ __device__ inline void padded_index(int p, int* iw, int* iwt)
 }
 
 // mode 0: Adam on P (with moments m, v, step t) then repack; mode 1: grad_out = summed gradient;
-// mode 2: repack only.
-__global__ void reduce_kernel(const float* partial, int n_waves, int mode, float* P, float* m, float* v, float lr,
-                              float b1, float b2, float eps, float wd, float bc1, float bc2, float* grad_out,
-                              unsigned short* W, unsigned short* Wlo, unsigned short* WT)
+// mode 2: repack only.  A block of 256 threads takes 64 parameters: thread group g (threads
+// 64 g .. 64 g + 63) sums the partials of the work-groups w = g mod 4 in order, and the four
+// group sums are added in the order g = 0..3, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) reduce_kernel(const float* partial, int n_waves, int mode, float* P, float* m,
+                                                     float* v, float lr, float b1, float b2, float eps, float wd,
+                                                     float bc1, float bc2, float* grad_out, unsigned short* W,
+                                                     unsigned short* Wlo, unsigned short* WT)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N_PARAMS) return;
+    __shared__ float part4[4][64];
+    const int grp = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
     if (mode != 2) {
-        float g = 0.0f;
-        for (int w = 0; w < n_waves; ++w) g += partial[(size_t)w * N_PARAMS + p];
+        float a0 = 0.0f, a1 = 0.0f;   // alternate work-groups of the group, two loads in flight
+        if (p < N_PARAMS) {
+            int w = grp;
+            for (; w + 4 < n_waves; w += 8) {
+                a0 += partial[(size_t)w * N_PARAMS + p];
+                a1 += partial[(size_t)(w + 4) * N_PARAMS + p];
+            }
+            if (w < n_waves) a0 += partial[(size_t)w * N_PARAMS + p];
+        }
+        part4[grp][threadIdx.x & 63] = a0 + a1;
+        __syncthreads();
+    }
+    if (grp != 0 || p >= N_PARAMS) return;
+    if (mode != 2) {
+        const int q = threadIdx.x;
+        const float g = ((part4[0][q] + part4[1][q]) + part4[2][q]) + part4[3][q];
         if (mode == 1) {
             grad_out[p] = g;
             return;
@@ -412,8 +502,8 @@ hipError_t mlp_launch_train(const mlp::Net& net, const float* X, const float* T,
                             long long n, int mode, float inv_batch, float* partial, float* loss, int waves,
                             hipStream_t st)
 {
-    hipLaunchKernelGGL(mlp::train_kernel, dim3(waves), dim3(64), mlp::TR_LDS, st, net, X, T, DY, base, n, mode,
-                       inv_batch, partial, loss);
+    hipLaunchKernelGGL(mlp::train_kernel, dim3(waves), dim3(256), mlp::TR_LDS + mlp::tw::BYTES, st, net, X, T,
+                       DY, base, n, mode, inv_batch, partial, loss);
     return hipGetLastError();
 }
 
@@ -421,7 +511,7 @@ hipError_t mlp_launch_reduce(const float* partial, int n_waves, int mode, float*
                              float b1, float b2, float eps, float wd, float bc1, float bc2, float* grad_out,
                              unsigned short* W, unsigned short* Wlo, unsigned short* WT, hipStream_t st)
 {
-    hipLaunchKernelGGL(mlp::reduce_kernel, dim3((mlp::N_PARAMS + 255) / 256), dim3(256), 0, st, partial, n_waves, mode,
+    hipLaunchKernelGGL(mlp::reduce_kernel, dim3((mlp::N_PARAMS + 63) / 64), dim3(256), 0, st, partial, n_waves, mode,
                        P, m, v, lr, b1, b2, eps, wd, bc1, bc2, grad_out, W, Wlo, WT);
     return hipGetLastError();
 }

@@ -115,7 +115,7 @@ raptor_status raptor_mlp_default_cfg(raptor_mlp_train_cfg* c)
     c->n_val = 100000;
     c->epochs = 120;
     c->batch = 4096;
-    c->lr = 3e-3f;
+    c->lr = 6e-3f;
     c->lr_final = 2e-5f;
     c->beta1 = 0.9f;
     c->beta2 = 0.999f;
