@@ -294,9 +294,9 @@ enum { RAPTOR_MLP_PARAMS = 12866 };
 typedef struct {
     int64_t n_train;             /* training samples generated on the device (default 1e7) */
     int64_t n_val;               /* validation samples (default 1e5) */
-    int32_t epochs;              /* passes over the training samples (default 120) */
-    int32_t batch;               /* samples per Adam step, a multiple of 64 (default 4096) */
-    float lr, lr_final;          /* Adam step size, cosine-decayed from lr to lr_final (defaults 6e-3, 2e-5) */
+    int32_t epochs;              /* passes over the training samples (default 150) */
+    int32_t batch;               /* samples per Adam step, a multiple of 64 (default 6144) */
+    float lr, lr_final;          /* Adam step size, cosine-decayed from lr to lr_final (defaults 8e-3, 2e-5) */
     float beta1, beta2, adam_eps, weight_decay;
     uint64_t train_seed, val_seed;
     int32_t form;                /* forward form used in training and validation: SPLIT or BF16 */

@@ -82,16 +82,22 @@ __global__ void exact_kernel(K2Table k2, long long n, const float* raw, float* o
 
 // ------------------------------------------------------------------------------------------
 // Training: one work-group of four waves per 64 samples.
-// LDS: Z[4][64][64] pre-activations (BF16, [sample][feature]), two dZ buffers [64][64] (BF16),
-// X[64][16] inputs (BF16), 8 loss floats.
+// LDS: Z[4][64][ZS] pre-activations (BF16, [sample][feature]), two dZ buffers [64][ZS] (BF16),
+// X[64][XS] inputs (BF16), 8 loss floats.  Rows are padded by four BF16 (8 bytes): a fragment
+// read or store touches 16 rows, or 4 rows four samples apart, and with the padding those start
+// in different banks.
 // ------------------------------------------------------------------------------------------
-constexpr int TR_LDS = (4 * 64 * 64 + 2 * 64 * 64 + 64 * 16) * 2 + 8 * 4;
+constexpr int ZS = 68, XS = 20, ZL = 64 * ZS;   // row strides and the size of one [64][ZS] array
+constexpr int TR_LDS = (4 * ZL + 2 * ZL + 64 * XS) * 2 + 8 * 4;
 
+// Work-group barrier that orders LDS accesses only.  The fences are limited to the local address
+// space: a plain work-group fence would also wait for every global store in flight (the partial
+// gradients), which the other waves never read.
 __device__ inline void lds_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ inline void store4(unsigned short* p, float a, float b, float c, float d)
@@ -121,34 +127,45 @@ __device__ inline bf16x4 frag_samples(const unsigned short* M, int rs, int f0, i
 }
 
 // dW[out][in] = sum_s dZ[s][out] H[s][in] over the work-group's 64 samples; writes the partial.
-// dZ: [64][64] BF16 (first out_tiles*16 features used); H: [64][rs] BF16 (pre-activations if
+// dZ: [64][ZS] BF16 (first out_tiles*16 features used); H: [64][rs] BF16 (pre-activations if
 // ACT, raw inputs otherwise); db[out] = sum_s dZ[s][out].
-// The four waves of a work-group share the (out tile, in tile) pairs, pair i on wave i mod 4, and
-// the bias entries, out = 16 wave + (lane < 16 ? lane : -): each entry is computed by one wave,
-// with the same instruction sequence whichever wave it is.
+// in_tiles is 4 or 1.  With four input tiles, wave w takes input tile w against every output
+// tile, so that it reads (and activates) its H fragments once; with one, wave w takes output
+// tile w.  The bias of output tile t is summed by wave t from the dZ fragments it already holds:
+// each lane adds its sixteen samples, then the four lane groups are combined in a fixed tree.
+// Every entry is computed by one wave, with the same instruction sequence whichever wave it is.
+// The partials are written with non-temporal stores: only the reduction reads them, once.
 template <bool ACT>
 __device__ inline void weight_grad(const unsigned short* dZ, const unsigned short* H, int rs, int out_tiles,
                                    int in_tiles, int out_dim, int in_dim, float* gW, float* gb, int wave, int lane)
 {
     const int g4 = 4 * (lane >> 4), n = lane & 15;
-    for (int pr = wave; pr < out_tiles * in_tiles; pr += 4) {
-        const int mt = pr / in_tiles, nt = pr % in_tiles;
-        f32x4 acc = f32x4{0, 0, 0, 0};
+    const int nt = in_tiles == 4 ? wave : 0;
+    const int mt0 = in_tiles == 4 ? 0 : wave, mt1 = in_tiles == 4 ? out_tiles : wave + 1;
+    bf16x4 hf[4];
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-            acc = mfma(frag_samples<false>(dZ, 64, 16 * mt, kt, lane), frag_samples<ACT>(H, rs, 16 * nt, kt, lane), acc);
-        const int in = 16 * nt + n;
+    for (int kt = 0; kt < 4; ++kt) hf[kt] = frag_samples<ACT>(H, rs, 16 * nt, kt, lane);
+    const int in = 16 * nt + n;
+    for (int mt = mt0; mt < mt1; ++mt) {
+        f32x4 acc = f32x4{0, 0, 0, 0};
+        float bs = 0.0f;
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            const bf16x4 d = frag_samples<false>(dZ, ZS, 16 * mt, kt, lane);
+            acc = mfma(d, hf[kt], acc);
+            bs += (bf2f((unsigned short)d.x) + bf2f((unsigned short)d.y)) +
+                  (bf2f((unsigned short)d.z) + bf2f((unsigned short)d.w));
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int out = 16 * mt + g4 + j;
-            if (out < out_dim && in < in_dim) gW[out * in_dim + in] = acc[j];
+            if (out < out_dim && in < in_dim) __builtin_nontemporal_store(acc[j], gW + out * in_dim + in);
         }
-    }
-    const int out = 16 * wave + lane;
-    if (lane < 16 && out < out_dim) {
-        float s = 0.0f;
-        for (int smp = 0; smp < 64; ++smp) s += bf2f(dZ[smp * 64 + out]);
-        gb[out] = s;
+        if (mt == wave) {
+            bs += __shfl_xor(bs, 16, 64);
+            bs += __shfl_xor(bs, 32, 64);
+            if (lane < 16 && 16 * mt + n < out_dim) __builtin_nontemporal_store(bs, gb + 16 * mt + n);
+        }
     }
 }
 
@@ -158,13 +175,13 @@ __device__ inline void backprop_block(const unsigned short* WT, int out_pad, int
 {
     const int g4 = 4 * (lane >> 4), s = 16 * cb + (lane & 15);
     bf16x4 b[4];
-    for (int kt = 0; kt < k_tiles; ++kt) b[kt] = *reinterpret_cast<const bf16x4*>(dZ + s * 64 + 16 * kt + g4);
+    for (int kt = 0; kt < k_tiles; ++kt) b[kt] = *reinterpret_cast<const bf16x4*>(dZ + s * ZS + 16 * kt + g4);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = f32x4{0, 0, 0, 0};
         for (int kt = 0; kt < k_tiles; ++kt) acc = mfma(frag_a(WT, out_pad, 16 * mt, 16 * kt, lane), b[kt], acc);
-        const f32x4 z = load4(Zp + s * 64 + 16 * mt + g4);
-        store4(dZp + s * 64 + 16 * mt + g4, acc.x * silu_grad(z.x), acc.y * silu_grad(z.y), acc.z * silu_grad(z.z),
+        const f32x4 z = load4(Zp + s * ZS + 16 * mt + g4);
+        store4(dZp + s * ZS + 16 * mt + g4, acc.x * silu_grad(z.x), acc.y * silu_grad(z.y), acc.z * silu_grad(z.z),
                acc.w * silu_grad(z.w));
     }
 }
@@ -182,44 +199,74 @@ constexpr int t_size(int L) { return in_pad(L) * t_stride(L); }
 constexpr int w_off(int L) { return L == 0 ? 0 : w_off(L - 1) + w_size(L - 1); }
 constexpr int t_off(int L) { return L == 0 ? 0 : t_off(L - 1) + t_size(L - 1); }
 constexpr int COPY = w_off(5);   // BF16 per copy (W, W lo and WT have the same size)
-constexpr int BYTES = 3 * COPY * 2;
+constexpr int BYTES = 3 * COPY * 2;   // the biases follow at this byte offset
+constexpr int BIAS_BYTES = 260 * 4;
 static_assert(COPY == t_off(5), "W and WT copies of the same size");
 }  // namespace tw
 constexpr int PW_OF[5] = {PW1, PW2, PW3, PW4, PW5};
 
-// Copy the padded global layouts into the LDS layout, eight bytes per move.
+// Copy the padded global layouts into the LDS layout.  The three arrays are read in 16-byte
+// chunks, chunk c of each array by thread c mod 256, all loads issued before the first LDS store
+// so that their latencies overlap; each chunk lies in one row of one layer (rows are 16 or 64
+// BF16 long) and goes to LDS as two 8-byte stores.  The FP32 biases follow as float [4][64]
+// (hidden layers) and [2] (output) at byte offset tw::BYTES.  Requires 256 threads.
 __device__ inline void stage_train_weights(const Net& net, unsigned short* dst)
 {
-    for (int L = 0; L < 5; ++L) {
-        const int wr = tw::out_pad(L), wc = tw::in_pad(L) / 4;   // W rows, 8-byte chunks per row
-        for (int i = threadIdx.x; i < wr * wc; i += blockDim.x) {
-            const int r = i / wc, c = 4 * (i % wc);
-            const int d = tw::w_off(L) + r * tw::w_stride(L) + c;
-            const int sidx = PW_OF[L] + r * tw::in_pad(L) + c;
-            *reinterpret_cast<bf16x4*>(dst + d) = *reinterpret_cast<const bf16x4*>(net.W + sidx);
-            *reinterpret_cast<bf16x4*>(dst + tw::COPY + d) = *reinterpret_cast<const bf16x4*>(net.Wlo + sidx);
-        }
-        const int tr = tw::in_pad(L), tc = tw::out_pad(L) / 4;
-        for (int i = threadIdx.x; i < tr * tc; i += blockDim.x) {
-            const int r = i / tc, c = 4 * (i % tc);
-            *reinterpret_cast<bf16x4*>(dst + 2 * tw::COPY + tw::t_off(L) + r * tw::t_stride(L) + c) =
-                *reinterpret_cast<const bf16x4*>(net.WT + PW_OF[L] + r * tw::out_pad(L) + c);
-        }
+    const int t = threadIdx.x;
+    const float hb = net.P[hidden_bias_off(t >> 6) + (t & 63)];
+    const float ob = t < 2 ? net.P[OFF_B5 + t] : 0.0f;
+    constexpr int CH = PW_TOTAL / (8 * 256);   // chunks per thread and array
+    static_assert(PW_TOTAL % (8 * 256) == 0, "whole chunks per thread");
+    static_assert(tw::in_pad(0) == 16 && tw::in_pad(1) == 64 && tw::out_pad(4) == 16 && tw::out_pad(3) == 64,
+                  "row lengths taken as 2^4 and 2^6 below");
+    uint4 w[CH], wl[CH], wt[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int e = 8 * ((int)threadIdx.x + 256 * k);
+        w[k] = *reinterpret_cast<const uint4*>(net.W + e);
+        wl[k] = *reinterpret_cast<const uint4*>(net.Wlo + e);
+        wt[k] = *reinterpret_cast<const uint4*>(net.WT + e);
     }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int e = 8 * ((int)threadIdx.x + 256 * k);
+        const int L = (e >= PW2) + (e >= PW3) + (e >= PW4) + (e >= PW5);
+        const int pw = L == 0 ? PW1 : L == 1 ? PW2 : L == 2 ? PW3 : L == 3 ? PW4 : PW5;
+        const int wof = L == 0 ? tw::w_off(0) : L == 1 ? tw::w_off(1) : L == 2 ? tw::w_off(2)
+                      : L == 3 ? tw::w_off(3) : tw::w_off(4);
+        const int tof = L == 0 ? tw::t_off(0) : L == 1 ? tw::t_off(1) : L == 2 ? tw::t_off(2)
+                      : L == 3 ? tw::t_off(3) : tw::t_off(4);
+        const int lin = L == 0 ? 4 : 6, lout = L == 4 ? 4 : 6;   // log2 of in_pad, out_pad
+        const int q = e - pw;
+        const int dw = wof + (q >> lin) * ((1 << lin) + 4) + (q & ((1 << lin) - 1));
+        const int dt = 2 * tw::COPY + tof + (q >> lout) * ((1 << lout) + 4) + (q & ((1 << lout) - 1));
+        uint2* pw0 = reinterpret_cast<uint2*>(dst + dw);
+        uint2* pw1 = reinterpret_cast<uint2*>(dst + tw::COPY + dw);
+        uint2* pt = reinterpret_cast<uint2*>(dst + dt);
+        pw0[0] = uint2{w[k].x, w[k].y};
+        pw0[1] = uint2{w[k].z, w[k].w};
+        pw1[0] = uint2{wl[k].x, wl[k].y};
+        pw1[1] = uint2{wl[k].z, wl[k].w};
+        pt[0] = uint2{wt[k].x, wt[k].y};
+        pt[1] = uint2{wt[k].z, wt[k].w};
+    }
+    float* bias = reinterpret_cast<float*>(dst + 3 * tw::COPY);
+    bias[t] = hb;
+    if (t < 2) bias[256 + t] = ob;
 }
 
-// Weight source of forward_block reading that LDS copy (biases from the FP32 parameters).
+// Weight source of forward_block reading that LDS copy.
 template <bool SPLIT>
 struct LdsTrainWeights {
     const unsigned short* lw;
-    const float* P;
+    const float* lb;   // staged biases
     __device__ inline Split w(int layer, int mt, int kt, int lane) const
     {
         return frag_w<SPLIT>(lw + tw::w_off(layer), lw + tw::COPY + tw::w_off(layer),
                              tw::w_stride(layer), 16 * mt, 16 * kt, lane);
     }
-    __device__ inline const float* bias(int layer) const { return P + hidden_bias_off(layer); }
-    __device__ inline float out_bias(int o) const { return P[OFF_B5 + o]; }
+    __device__ inline const float* bias(int layer) const { return lb + 64 * layer; }
+    __device__ inline float out_bias(int o) const { return lb[256 + o]; }
 };
 
 // mode 0: gradient of the mean squared error against T (standardised targets), loss sums to
@@ -233,65 +280,69 @@ __global__ void __launch_bounds__(256) train_kernel(Net net, const float* X, con
                                                     long long n, int mode, float inv_batch, float* partial, float* loss)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    unsigned short* Z = reinterpret_cast<unsigned short*>(lds);   // [4][64][64]
-    unsigned short* dA = Z + 4 * 64 * 64;                          // [64][64]
-    unsigned short* dB = dA + 64 * 64;                              // [64][64]
-    unsigned short* Xs = dB + 64 * 64;                              // [64][16]
-    float* lred = reinterpret_cast<float*>(Xs + 64 * 16);           // [4][2] per-wave loss sums
+    unsigned short* Z = reinterpret_cast<unsigned short*>(lds);   // [4][64][ZS]
+    unsigned short* dA = Z + 4 * ZL;                               // [64][ZS]
+    unsigned short* dB = dA + ZL;                                  // [64][ZS]
+    unsigned short* Xs = dB + ZL;                                  // [64][XS]
+    float* lred = reinterpret_cast<float*>(Xs + 64 * XS);          // [4][2] per-wave loss sums
     unsigned short* lw = reinterpret_cast<unsigned short*>(lds + TR_LDS);   // tw layout
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    stage_train_weights(net, lw);
-    lds_sync();
     const int g4 = 4 * (lane >> 4), nl = lane & 15;
     const long long s0 = base + 64ll * blockIdx.x;
     float* gw = partial + (size_t)blockIdx.x * N_PARAMS;
     float l0 = 0.0f, l1 = 0.0f;
+    // this lane's sample of the wave's column block; its input and target are read before the
+    // weights are staged so that the two latencies overlap
+    const int s = 16 * wave + nl;
+    const long long gs = s0 + s;
+    const bool valid = gs < n;
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f, y0 = 0.0f, y1 = 0.0f;
+    if (valid && lane < 16) {
+        x0 = X[3 * gs];
+        x1 = X[3 * gs + 1];
+        x2 = X[3 * gs + 2];
+        const float* Y = mode == 0 ? T : DY;
+        y0 = Y[2 * gs];
+        y1 = Y[2 * gs + 1];
+    }
+    stage_train_weights(net, lw);
+    lds_sync();
 
     // ---- forward of this wave's column block; keep pre-activations, form dY = dZ5
     {
-        const int cb = wave;
-        const int s = 16 * cb + nl;
-        const long long gs = s0 + s;
-        const bool valid = gs < n;
-        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-        if (valid && lane < 16) {
-            x0 = X[3 * gs];
-            x1 = X[3 * gs + 1];
-            x2 = X[3 * gs + 2];
-        }
         Split bx;
         bx.hi = (lane < 16) ? pack4(x0, x1, x2, 0.0f) : bf16x4{0, 0, 0, 0};
         bx.lo = (lane < 16) ? split4(x0, x1, x2, 0.0f).lo : bf16x4{0, 0, 0, 0};
-        store4(Xs + s * 16 + g4, lane < 16 ? x0 : 0.0f, lane < 16 ? x1 : 0.0f, lane < 16 ? x2 : 0.0f, 0.0f);
+        store4(Xs + s * XS + g4, lane < 16 ? x0 : 0.0f, lane < 16 ? x1 : 0.0f, lane < 16 ? x2 : 0.0f, 0.0f);
         f32x4 z[16];
-        const f32x4 o = forward_block<true>(LdsTrainWeights<true>{lw, net.P}, bx, lane, z);
+        const f32x4 o = forward_block<true>(LdsTrainWeights<true>{lw, reinterpret_cast<const float*>(lw + 3 * tw::COPY)}, bx, lane, z);
 #pragma unroll
         for (int L = 0; L < 4; ++L)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const f32x4 v = z[4 * L + mt];
-                store4(Z + L * 4096 + s * 64 + 16 * mt + g4, v.x, v.y, v.z, v.w);
+                store4(Z + L * ZL + s * ZS + 16 * mt + g4, v.x, v.y, v.z, v.w);
             }
         float d0 = 0.0f, d1 = 0.0f;
         if (lane < 16 && valid) {
             if (mode == 0) {
-                const float e0 = o.x - T[2 * gs], e1 = o.y - T[2 * gs + 1];
+                const float e0 = o.x - y0, e1 = o.y - y1;
                 l0 = e0 * e0;
                 l1 = e1 * e1;
                 d0 = e0 * inv_batch;
                 d1 = e1 * inv_batch;
             } else {
-                d0 = DY[2 * gs];
-                d1 = DY[2 * gs + 1];
+                d0 = y0;
+                d1 = y1;
             }
         }
-        store4(dA + s * 64 + g4, d0, d1, 0.0f, 0.0f);   // dZ5 in features 0..15 (lanes >= 16 write zeros)
+        store4(dA + s * ZS + g4, d0, d1, 0.0f, 0.0f);   // dZ5 in features 0..15 (lanes >= 16 write zeros)
     }
     lds_sync();
     // ---- layer 5 (64 -> 2)
-    weight_grad<true>(dA, Z + 3 * 4096, 64, 1, 4, 2, 64, gw + OFF_W5, gw + OFF_B5, wave, lane);
+    weight_grad<true>(dA, Z + 3 * ZL, ZS, 1, 4, 2, 64, gw + OFF_W5, gw + OFF_B5, wave, lane);
     const unsigned short* lwt = lw + 2 * tw::COPY;
-    backprop_block(lwt + tw::t_off(4), tw::t_stride(4), 1, dA, Z + 3 * 4096, dB, wave, lane);
+    backprop_block(lwt + tw::t_off(4), tw::t_stride(4), 1, dA, Z + 3 * ZL, dB, wave, lane);
     lds_sync();
     // ---- layers 4, 3, 2
     unsigned short* cur = dB;
@@ -299,8 +350,8 @@ __global__ void __launch_bounds__(256) train_kernel(Net net, const float* X, con
     const int offw[3] = {OFF_W4, OFF_W3, OFF_W2}, offb[3] = {OFF_B4, OFF_B3, OFF_B2};
     for (int i = 0; i < 3; ++i) {
         const int L = 3 - i;   // pre-activation index of this layer's input: Z[L - 1]
-        weight_grad<true>(cur, Z + (L - 1) * 4096, 64, 4, 4, 64, 64, gw + offw[i], gw + offb[i], wave, lane);
-        backprop_block(lwt + tw::t_off(3 - i), tw::t_stride(3 - i), 4, cur, Z + (L - 1) * 4096, nxt,
+        weight_grad<true>(cur, Z + (L - 1) * ZL, ZS, 4, 4, 64, 64, gw + offw[i], gw + offb[i], wave, lane);
+        backprop_block(lwt + tw::t_off(3 - i), tw::t_stride(3 - i), 4, cur, Z + (L - 1) * ZL, nxt,
                        wave, lane);
         lds_sync();
         unsigned short* t = cur;
@@ -308,7 +359,7 @@ __global__ void __launch_bounds__(256) train_kernel(Net net, const float* X, con
         nxt = t;
     }
     // ---- layer 1 (3 -> 64)
-    weight_grad<false>(cur, Xs, 16, 4, 1, 64, 3, gw + OFF_W1, gw + OFF_B1, wave, lane);
+    weight_grad<false>(cur, Xs, XS, 4, 1, 64, 3, gw + OFF_W1, gw + OFF_B1, wave, lane);
     if (mode == 0) {
         // per-wave sums in a fixed tree, then the four waves in order
         for (int o = 32; o > 0; o >>= 1) {
@@ -343,48 +394,70 @@ __device__ inline void padded_index(int p, int* iw, int* iwt)
 }
 
 // mode 0: Adam on P (with moments m, v, step t) then repack; mode 1: grad_out = summed gradient;
-// mode 2: repack only.  A block of 256 threads takes 64 parameters: thread group g (threads
-// 64 g .. 64 g + 63) sums the partials of the work-groups w = g mod 4 in order, and the four
-// group sums are added in the order g = 0..3, so the result does not depend on scheduling.
+// mode 2: repack only.  A block of 256 threads takes 32 parameters: thread group g (threads
+// 32 g .. 32 g + 31) sums the partials of the work-groups w = g mod 8 in order, and the eight
+// group sums are added in a fixed tree, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(256) reduce_kernel(const float* partial, int n_waves, int mode, float* P, float* m,
                                                      float* v, float lr, float b1, float b2, float eps, float wd,
                                                      float bc1, float bc2, float* grad_out, unsigned short* W,
                                                      unsigned short* Wlo, unsigned short* WT)
 {
-    __shared__ float part4[4][64];
-    const int grp = threadIdx.x >> 6;
-    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
-    if (mode != 2) {
-        float a0 = 0.0f, a1 = 0.0f;   // alternate work-groups of the group, two loads in flight
-        if (p < N_PARAMS) {
-            int w = grp;
-            for (; w + 4 < n_waves; w += 8) {
-                a0 += partial[(size_t)w * N_PARAMS + p];
-                a1 += partial[(size_t)(w + 4) * N_PARAMS + p];
-            }
-            if (w < n_waves) a0 += partial[(size_t)w * N_PARAMS + p];
+    __shared__ float part8[8][32];
+    const int grp = threadIdx.x >> 5;
+    const int p = blockIdx.x * 32 + (threadIdx.x & 31);
+    const bool owner = grp == 0 && p < N_PARAMS;
+    // parameters and moments (mode 0) or parameters (mode 2) are read before the partials, so
+    // that the latencies overlap; mode 1 has neither (P, m, v may be null)
+    float p0 = 0.0f, m0 = 0.0f, v0 = 0.0f;
+    if (owner && mode != 1) {
+        p0 = P[p];
+        if (mode == 0) {
+            m0 = m[p];
+            v0 = v[p];
         }
-        part4[grp][threadIdx.x & 63] = a0 + a1;
+    }
+    if (mode != 2) {
+        // work-groups w + 8 j (j < R) of the group go to accumulator j: R loads in flight
+        constexpr int R = 12;
+        float a[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[j] = 0.0f;
+        if (p < N_PARAMS) {
+            for (int w = grp; w < n_waves; w += 8 * R) {
+                float x[R];
+#pragma unroll
+                for (int j = 0; j < R; ++j) x[j] = w + 8 * j < n_waves ? partial[(size_t)(w + 8 * j) * N_PARAMS + p] : 0.0f;
+#pragma unroll
+                for (int j = 0; j < R; ++j) a[j] += x[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a[j] += a[j + 6];   // fixed tree: 12 -> 6 -> 3 -> 1
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a[j] += a[j + 3];
+        part8[grp][threadIdx.x & 31] = (a[0] + a[1]) + a[2];
         __syncthreads();
     }
-    if (grp != 0 || p >= N_PARAMS) return;
+    if (!owner) return;
+    float w = p0;
     if (mode != 2) {
         const int q = threadIdx.x;
-        const float g = ((part4[0][q] + part4[1][q]) + part4[2][q]) + part4[3][q];
+        const float g = ((part8[0][q] + part8[1][q]) + (part8[2][q] + part8[3][q])) +
+                        ((part8[4][q] + part8[5][q]) + (part8[6][q] + part8[7][q]));
         if (mode == 1) {
             grad_out[p] = g;
             return;
         }
-        const float mm = b1 * m[p] + (1.0f - b1) * g;
-        const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+        const float mm = b1 * m0 + (1.0f - b1) * g;
+        const float vv = b2 * v0 + (1.0f - b2) * g * g;
         m[p] = mm;
         v[p] = vv;
-        P[p] -= lr * ((mm / bc1) / (sqrtf(vv / bc2) + eps) + wd * P[p]);
+        w = p0 - lr * ((mm / bc1) / (sqrtf(vv / bc2) + eps) + wd * p0);
+        P[p] = w;
     }
     int iw, iwt;
     padded_index(p, &iw, &iwt);
     if (iw >= 0) {
-        const float w = P[p];
         const unsigned short hi = f2bf(w);
         W[iw] = hi;
         Wlo[iw] = f2bf(w - bf2f(hi));
@@ -502,7 +575,7 @@ hipError_t mlp_launch_train(const mlp::Net& net, const float* X, const float* T,
                             long long n, int mode, float inv_batch, float* partial, float* loss, int waves,
                             hipStream_t st)
 {
-    hipLaunchKernelGGL(mlp::train_kernel, dim3(waves), dim3(256), mlp::TR_LDS + mlp::tw::BYTES, st, net, X, T,
+    hipLaunchKernelGGL(mlp::train_kernel, dim3(waves), dim3(256), mlp::TR_LDS + mlp::tw::BYTES + mlp::tw::BIAS_BYTES, st, net, X, T,
                        DY, base, n, mode, inv_batch, partial, loss);
     return hipGetLastError();
 }
@@ -511,7 +584,7 @@ hipError_t mlp_launch_reduce(const float* partial, int n_waves, int mode, float*
                              float b1, float b2, float eps, float wd, float bc1, float bc2, float* grad_out,
                              unsigned short* W, unsigned short* Wlo, unsigned short* WT, hipStream_t st)
 {
-    hipLaunchKernelGGL(mlp::reduce_kernel, dim3((mlp::N_PARAMS + 63) / 64), dim3(256), 0, st, partial, n_waves, mode,
+    hipLaunchKernelGGL(mlp::reduce_kernel, dim3((mlp::N_PARAMS + 31) / 32), dim3(256), 0, st, partial, n_waves, mode,
                        P, m, v, lr, b1, b2, eps, wd, bc1, bc2, grad_out, W, Wlo, WT);
     return hipGetLastError();
 }

@@ -113,9 +113,9 @@ raptor_status raptor_mlp_default_cfg(raptor_mlp_train_cfg* c)
     std::memset(c, 0, sizeof *c);
     c->n_train = 10000000;
     c->n_val = 100000;
-    c->epochs = 120;
-    c->batch = 4096;
-    c->lr = 6e-3f;
+    c->epochs = 150;
+    c->batch = 6144;
+    c->lr = 8e-3f;
     c->lr_final = 2e-5f;
     c->beta1 = 0.9f;
     c->beta2 = 0.999f;
