@@ -44,6 +44,7 @@ struct Transfer<double> {
     // per-sample, frequency-independent part
     double ne, the, bf, sinb, ln_k2, ds, inr3, nr;
     bool emits;
+    bool live;   // the sample contributes (a positive fluid-frame frequency)
     __device__ inline void setup(const TraceParams& p, const double fl[4], double nr_, double cosb, double dsv)
     {
         ne = fl[0]; the = fl[1]; bf = fl[2];
@@ -71,6 +72,15 @@ struct Transfer<double> {
         }
         pl::step_source(j, al, S, ds, inr3, A, dtau);
     }
+    // frequencies nu_obs[0 .. cnt) of up to G (entries g >= cnt are left untouched)
+    template <int G>
+    __device__ inline void contributions(const TraceParams& p, const double* nu_obs, int cnt, double* A,
+                                         double* dtau) const
+    {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (g < cnt) contribution(p, nu_obs[g], A[g], dtau[g]);
+    }
 };
 
 // FP32 transfer.  The coefficients j, alpha, S and the step's contribution are float
@@ -89,6 +99,7 @@ struct Transfer<float> {
     double nr_inv_nus;   // nu_r / nu_s: X = nu_obs nu_r / nu_s in double
     double nr;
     bool emits;
+    bool live;   // the sample contributes (a positive fluid-frame frequency)
     __device__ inline void setup(const TraceParams& p, const double fl[4], double nr_, double cosb, double dsv)
     {
         ne = (float)fl[0];
@@ -109,39 +120,62 @@ struct Transfer<float> {
     }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
+        contributions<1>(p, &nu_obs, 1, &A, &dtau);
+    }
+    // Frequencies nu_obs[0 .. cnt) of up to G at once, written without branches so that the G
+    // dependency chains interleave; entries g >= cnt, and frequencies whose emission is below
+    // exp(-1e8), are left untouched.
+    template <int G>
+    __device__ inline void contributions(const TraceParams& p, const double* nu_obs, int cnt, double* A,
+                                         double* dtau) const
+    {
         if (p.closure == CL_CONST) {
             const float j = (float)p.const_j, al = (float)p.const_alpha;
             float Af, dtf;
             pl::step_source(j, al, al > 0.0f ? j / al : 0.0f, ds, inr3, Af, dtf);
-            A = Af;
-            dtau = dtf;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (g < cnt) {
+                    A[g] = Af;
+                    dtau[g] = dtf;
+                }
+            }
             return;
         }
         if (!emits) return;
-        const double X = nu_obs * nr_inv_nus;
-        if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
-        const double tt = rt::cbrt_refined(X);
-        // exp(-(ln K2 + tt)) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in
-        // double too, and the exponent is kept above -1000 so that the scale stays finite
-        const double z = ::fmax(::fmin((tt + ln_k2) * 1.4426950408889634, 1100.0), -1000.0);
-        const double n = __builtin_rint(z);
-        const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
-        const double scale = __builtin_ldexp(1.0, -(int)n);
-        const float t = (float)tt;
-        const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
-        const float jm = 1.1396857174835936e-29f * ne * nu_s * t * tc * tc * em;   // j = jm 2^-n
-        const float nuf = (float)(nu_obs * nr);
-        const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
-        const float q3 = q * q * q;                               // 2 h nu^3 / c^2
-        const float em1 = rt::expm1_f((float)pl::H_OVER_MEC2 * nuf * inv_the);
-        const float S = q3 * rt::rcpf_nr(em1);                    // B_nu
-        const float dtm = jm * em1 * rt::rcpf_nr(q3) * ds;        // dtau = dtm 2^-n
-        dtau = (double)dtm * scale;
-        if (dtau > 1e-8) {
-            A = (double)(S * -rt::expm1_f(-(float)dtau) * inr3);
-        } else {
-            // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): S dtau = j ds to float precision
-            A = (double)(jm * ds * inr3) * scale;
+        bool ok[G];
+        double tt[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double X = nu_obs[g] * nr_inv_nus;
+            ok[g] = g < cnt && X < 1e24;   // beyond, exp(-X^1/3) < exp(-1e8): no emission, no absorption
+            tt[g] = rt::cbrt_refined(ok[g] ? X : 1.0);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            // exp(-(ln K2 + tt)) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in
+            // double too, and the exponent is kept above -1000 so that the scale stays finite
+            const double z = ::fmax(::fmin((tt[g] + ln_k2) * 1.4426950408889634, 1100.0), -1000.0);
+            const double n = __builtin_rint(z);
+            const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
+            const double scale = __builtin_ldexp(1.0, -(int)n);
+            const float t = (float)tt[g];
+            const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
+            const float jm = 1.1396857174835936e-29f * ne * nu_s * t * tc * tc * em;   // j = jm 2^-n
+            const float nuf = (float)(nu_obs[g] * nr);
+            const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
+            const float q3 = q * q * q;                               // 2 h nu^3 / c^2
+            const float em1 = rt::expm1_f((float)pl::H_OVER_MEC2 * nuf * inv_the);
+            const float S = q3 * rt::rcpf_nr(em1);                    // B_nu
+            const float dtm = jm * em1 * rt::rcpf_nr(q3) * ds;        // dtau = dtm 2^-n
+            const double dt = (double)dtm * scale;
+            // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): below 1e-8, S dtau = j ds to float precision
+            const double a_thick = (double)(S * -rt::expm1_f(-(float)dt) * inr3);
+            const double a_thin = (double)(jm * ds * inr3) * scale;
+            if (ok[g]) {
+                A[g] = dt > 1e-8 ? a_thick : a_thin;
+                dtau[g] = dt;
+            }
         }
     }
 };
@@ -205,11 +239,16 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Evaluate one queued sample: fluid state, fluid frame, closure, and per frequency the
-// attenuation-free contribution A (observed units) and the optical depth dtau of the step.
-template <int NNU, class TT>
-__device__ inline bool eval_sample(const TraceParams& p, const double* q, const LaneInfo& li, double* A,
-                                   double* dtau)
+// The frequency-independent part of a queued sample's evaluation: fluid state, fluid frame and
+// the transfer set-up.  A sample whose fluid-frame frequency is not positive (integration error
+// of a low-order integrator in the last step before the horizon) has no defined emission: its
+// transfer stays non-emitting and it adds nothing.  Returns whether the fluid frame fell back to
+// the ZAMO.
+// Frequencies evaluated together (independent dependency chains) by one lane.
+constexpr int FREQ_GROUP = 4;
+
+template <class TT>
+__device__ inline bool setup_sample(const TraceParams& p, const double* q, const LaneInfo& li, Transfer<TT>& tr)
 {
     const DevGrid& G = p.grids[li.grid];
     const double y[8] = {q[0], q[1], q[2], q[3], q[4], q[5], 0.0, q[6]};
@@ -217,20 +256,63 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
     pl::sample_fluid(G, p.slow_light, li.fast_snap, y, fl);
     double nr, cb;
     const bool zamo = pl::fluid_frame(li.a, li.a * li.a, p.M, y, q[8], q[9], fl[3], &nr, &cb);
+    tr.emits = false;
+    tr.live = nr > 0.0;
+    if (tr.live) tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+    return zamo;
+}
+
+// Evaluate one queued sample: fluid state, fluid frame, closure, and per frequency the
+// attenuation-free contribution A (observed units) and the optical depth dtau of the step.
+template <int NNU, class TT>
+__device__ inline bool eval_sample(const TraceParams& p, const double* q, const LaneInfo& li, double* A,
+                                   double* dtau)
+{
+    Transfer<TT> tr;
+    const bool zamo = setup_sample<TT>(p, q, li, tr);
 #pragma unroll
     for (int f = 0; f < NNU; ++f) {
         A[f] = 0.0;
         dtau[f] = 0.0;
     }
-    // a sample whose fluid-frame frequency is not positive (integration error of a low-order
-    // integrator in the last step before the horizon) has no defined emission: it adds nothing
-    if (!(nr > 0.0)) return zamo;
-    Transfer<TT> tr;
-    tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+    if (!tr.live) return zamo;
+    constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
 #pragma unroll
-    for (int f = 0; f < NNU; ++f)
-        if (f < li.n_nu) tr.contribution(p, p.nu[li.nu_base + f], A[f], dtau[f]);
+    for (int f = 0; f < NNU; f += G) {
+        if (f < li.n_nu) {
+            double nu[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) nu[g] = (f + g < li.n_nu) ? p.nu[li.nu_base + f + g] : 1.0;
+            tr.template contributions<G>(p, nu, li.n_nu - f, A + f, dtau + f);
+        }
+    }
     return zamo;
+}
+
+// A sample's transfer set-up kept in LDS between the two phases of a frequency-parallel round:
+// the bytes of Transfer<TT> in the sample's queue slot, in the fields the evaluation no longer
+// needs (every field but the step length, which the fold still reads).
+constexpr int SETUP_FIELDS[9] = {0, 1, 2, 3, 4, 5, 6, 8, 9};
+template <class TT>
+struct SetupWords {
+    static constexpr int N = (int)((sizeof(Transfer<TT>) + 7) / 8);
+    static_assert(N <= 9, "the transfer set-up fits the sample's free queue fields");
+};
+template <class TT, int SLOTS>
+__device__ inline void store_setup(double* fields, int s, const Transfer<TT>& tr)
+{
+    double w[SetupWords<TT>::N];
+    __builtin_memcpy(w, &tr, sizeof(Transfer<TT>));
+#pragma unroll
+    for (int k = 0; k < SetupWords<TT>::N; ++k) fields[SETUP_FIELDS[k] * SLOTS + s] = w[k];
+}
+template <class TT, int SLOTS>
+__device__ inline void load_setup(const double* fields, int s, Transfer<TT>& tr)
+{
+    double w[SetupWords<TT>::N];
+#pragma unroll
+    for (int k = 0; k < SetupWords<TT>::N; ++k) w[k] = fields[SETUP_FIELDS[k] * SLOTS + s];
+    __builtin_memcpy(&tr, w, sizeof(Transfer<TT>));
 }
 
 // The learned closure's step contribution in FP32 transfer, by the scheme of Transfer<float>: the
@@ -351,6 +433,11 @@ trace_kernel(TraceParams p)
 {
     using Q = Queue<NNU, TT, MLPC, WPE>;
     constexpr int K = Q::K;
+    // Several frequencies and a one-sample queue: the ray's intensity and optical depth per
+    // frequency live in its row of the result area (I then tau, 2 NNU doubles) instead of
+    // registers, and every round is evaluated frequency-parallel, each (sample, frequency) pair
+    // folded into that row by the lane that computes it.
+    constexpr bool FUSED = !MLPC && K == 1 && NNU > 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     unsigned char* wbase = smem + (size_t)(threadIdx.x >> 6) * Q::PER_WAVE;
@@ -440,6 +527,10 @@ trace_kernel(TraceParams p)
                         have_acc = false;
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) { I[f] = 0.0; tau[f] = 0.0; }
+                        if (FUSED) {
+#pragma unroll
+                            for (int f = 0; f < 2 * NNU; ++f) res[lane * 2 * NNU + f] = 0.0;
+                        }
                         active = true;
                     }
                 }
@@ -542,6 +633,135 @@ trace_kernel(TraceParams p)
                 listed += (c < n_eval - listed) ? c : (n_eval - listed);
             }
             wave_lds_sync();
+            if (FUSED) {
+                // phase 1: lane i sets up sample i (fluid, frame, transfer) and leaves the set-up
+                // in the sample's queue slot (K = 1: slot = owner lane, n_eval <= 64)
+                bool zamo = false;
+                if (lane < n_eval) {
+                    const int s = slot_map[lane];
+                    double q[N_FIELDS];
+#pragma unroll
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                    Transfer<TT> tr;
+                    zamo = setup_sample<TT>(p, q, lane_info(p, lane_job[s]), tr);
+                    store_setup<TT, Q::SLOTS>(fields, s, tr);
+                }
+                c_zamo += __popcll(__ballot(zamo));
+                wave_lds_sync();
+                // phase 2: `per` consecutive lanes share a sample, lane c of them taking its
+                // frequencies [c n, (c + 1) n), n = ceil(n_nu / per): contribution, then the fold
+                // I += exp(-tau) A, tau += dtau into the owner's row
+                const unsigned per = n_eval >= 64 ? 1u : (64u / n_eval < (unsigned)NNU ? 64u / n_eval : (unsigned)NNU);
+                const unsigned mul = (65535u + per) / per;   // x / per = (x mul) >> 16 for x < 1024
+                const unsigned is = ((unsigned)lane * mul) >> 16;
+                const unsigned chunk = (unsigned)lane - is * per;
+                double tmin = 1e300, dtmax = 0.0;
+                if (is < n_eval) {
+                    const int s = slot_map[is];
+                    const LaneInfo li = lane_info(p, lane_job[s]);
+                    const int c = (int)(((unsigned)(li.n_nu + per - 1) * mul) >> 16);
+                    const int f0 = (int)chunk * c;
+                    const int f1 = (f0 + c < li.n_nu) ? f0 + c : li.n_nu;
+                    Transfer<TT> tr;
+                    load_setup<TT, Q::SLOTS>(fields, s, tr);
+                    double* Ir = res + s * 2 * NNU;
+                    double* Tr = Ir + NNU;
+                    constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
+                    int f = f0;
+                    for (; f + G <= f1; f += G) {
+                        double nu[G], A[G], dt[G];
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            nu[g] = p.nu[li.nu_base + f + g];
+                            A[g] = 0.0;
+                            dt[g] = 0.0;
+                        }
+                        if (tr.live) tr.template contributions<G>(p, nu, G, A, dt);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const double t0 = Tr[f + g];
+                            Ir[f + g] = Ir[f + g] + (double)attenuation<TT>(t0) * A[g];
+                            const double t1 = t0 + dt[g];
+                            Tr[f + g] = t1;
+                            tmin = ::fmin(tmin, t1);
+                            dtmax = ::fmax(dtmax, dt[g]);
+                        }
+                    }
+                    for (; f < f1; ++f) {
+                        double A = 0.0, dt = 0.0;
+                        if (tr.live) tr.contribution(p, p.nu[li.nu_base + f], A, dt);
+                        const double t0 = Tr[f];
+                        Ir[f] = Ir[f] + (double)attenuation<TT>(t0) * A;
+                        const double t1 = t0 + dt;
+                        Tr[f] = t1;
+                        tmin = ::fmin(tmin, t1);
+                        dtmax = ::fmax(dtmax, dt);
+                    }
+                }
+                // the sample's smallest optical depth and largest step depth over its frequencies:
+                // reduced over its `per` lanes onto the first, which leaves them in the slot's
+                // queue fields 8 and 9 (the set-up is no longer read)
+                for (unsigned off = 1; off < per; off <<= 1) {
+                    const double tm = __shfl_down(tmin, off, 64), dm = __shfl_down(dtmax, off, 64);
+                    if (chunk + off < per) {
+                        tmin = ::fmin(tmin, tm);
+                        dtmax = ::fmax(dtmax, dm);
+                    }
+                }
+                if (is < n_eval && chunk == 0) {
+                    const int s = slot_map[is];
+                    fields[8 * Q::SLOTS + s] = tmin;
+                    fields[9 * Q::SLOTS + s] = dtmax;
+                }
+            } else if (!MLPC && NNU > 1 && n_eval < 64) {
+                // fewer samples than lanes: the (sample, frequency) pairs are spread over the
+                // wave.  Lane i sets up sample i (fluid, frame, transfer) and leaves the set-up
+                // in the sample's queue slot; then `per` lanes share each sample, lane c of them
+                // taking its frequencies [c n, (c + 1) n), n = ceil(n_nu / per).
+                bool zamo = false;
+                if (lane < n_eval) {
+                    const int s = slot_map[lane];
+                    double q[N_FIELDS];
+#pragma unroll
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                    Transfer<TT> tr;
+                    zamo = setup_sample<TT>(p, q, lane_info(p, lane_job[s / K]), tr);
+                    store_setup<TT, Q::SLOTS>(fields, s, tr);
+                }
+                c_zamo += __popcll(__ballot(zamo));
+                wave_lds_sync();
+                const unsigned per = (64u / n_eval < (unsigned)NNU) ? 64u / n_eval : (unsigned)NNU;
+                const unsigned mul = (65535u + per) / per;   // x / per = (x mul) >> 16 for x < 1024
+                const unsigned is = ((unsigned)lane * mul) >> 16;
+                if (is < n_eval) {
+                    const int s = slot_map[is];
+                    const LaneInfo li = lane_info(p, lane_job[s / K]);
+                    const int c = (int)(((unsigned)(li.n_nu + per - 1) * mul) >> 16);
+                    const int f0 = (int)((unsigned)lane - is * per) * c;
+                    const int f1 = (f0 + c < li.n_nu) ? f0 + c : li.n_nu;
+                    Transfer<TT> tr;
+                    load_setup<TT, Q::SLOTS>(fields, s, tr);
+                    constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
+                    for (int f = f0; f < f1; f += G) {
+                        const int cnt = f1 - f;
+                        double nu[G], A[G], dt[G];
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            nu[g] = g < cnt ? p.nu[li.nu_base + f + g] : 1.0;
+                            A[g] = 0.0;
+                            dt[g] = 0.0;
+                        }
+                        if (tr.live) tr.template contributions<G>(p, nu, cnt, A, dt);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            if (g < cnt) {
+                                res[s * 2 * NNU + f + g] = A[g];
+                                res[s * 2 * NNU + NNU + f + g] = dt[g];
+                            }
+                        }
+                    }
+                }
+            } else
             for (unsigned r0 = 0; r0 < n_eval; r0 += 64) {
                 const unsigned i = r0 + lane;
                 if (MLPC) {
@@ -585,9 +805,18 @@ trace_kernel(TraceParams p)
             // the optical-depth cut-off the ray ends after the first sample that makes it opaque
             // at every frequency, and its later queued samples are dropped
             bool cut = false;
+            if (FUSED && take > 0) {
+                const int s = lane;   // K = 1
+                if (p.tau_step > 0.0) rt_rate = fields[9 * Q::SLOTS + s] / fields[7 * Q::SLOTS + s];
+                if (p.tau_cutoff > 0.0 && fields[8 * Q::SLOTS + s] >= p.tau_cutoff) {
+                    cut = true;
+                    status = RAY_OPAQUE;
+                    steps = qstep[0];
+                }
+            }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (k < take && !cut) {
+                if (!FUSED && k < take && !cut) {
                     const int s = lane * K + k;
                     double tmin = 1e300, dtmax = 0.0;
 #pragma unroll
@@ -639,7 +868,7 @@ trace_kernel(TraceParams p)
             double* o = p.out + J.out_base + pix;
 #pragma unroll
             for (int f = 0; f < NNU; ++f)
-                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : I[f];
+                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : (FUSED ? res[lane * 2 * NNU + f] : I[f]);
             if (p.ray_status) p.ray_status[J.pix_base + pix] = status;
             if (p.ray_steps) p.ray_steps[J.pix_base + pix] = steps;
             active = false;
