@@ -129,14 +129,16 @@ __host__ __device__ inline double rsqrt_nr(double x)
 __host__ __device__ inline float exp_mixed(double x)
 {
     const double z = x * 1.4426950408889634;
-    if (z < -160.0) return 0.0f;
-    const double n = __builtin_rint(z < 160.0 ? z : 160.0);
+    // below 2^-160 the result is 0 (selected, not branched on, so that independent calls can
+    // be interleaved); the clamp keeps the power of two in range there
+    const double n = __builtin_rint(z < 160.0 ? (z > -200.0 ? z : -200.0) : 160.0);
     const float f = (float)(z - n);
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
+    const float r = __builtin_ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
 #else
-    return std::ldexp(std::exp2(f), (int)n);
+    const float r = std::ldexp(std::exp2(f), (int)n);
 #endif
+    return z < -160.0 ? 0.0f : r;
 }
 
 // e^y - 1 in float: for |y| < 1 the Taylor series through y^11 (truncation below 2e-9 relative),

@@ -144,7 +144,7 @@ struct Transfer<float> {
         }
         if (!emits) return;
         bool ok[G];
-        double tt[G];
+        double tt[G], An[G], Dt[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const double X = nu_obs[g] * nr_inv_nus;
@@ -172,10 +172,18 @@ struct Transfer<float> {
             // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): below 1e-8, S dtau = j ds to float precision
             const double a_thick = (double)(S * -rt::expm1_f(-(float)dt) * inr3);
             const double a_thin = (double)(jm * ds * inr3) * scale;
-            if (ok[g]) {
-                A[g] = dt > 1e-8 ? a_thick : a_thin;
-                dtau[g] = dt;
-            }
+            An[g] = dt > 1e-8 ? a_thick : a_thin;
+            Dt[g] = dt;
+        }
+        // The G results are consumed here, unconditionally, by empty asm statements: without
+        // that the compiler sinks each chain into a branch on ok[g], one after another, and the
+        // chains no longer interleave.
+#pragma unroll
+        for (int g = 0; g < G; ++g) asm volatile("" ::"v"(An[g]), "v"(Dt[g]));
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            A[g] = ok[g] ? An[g] : A[g];
+            dtau[g] = ok[g] ? Dt[g] : dtau[g];
         }
     }
 };
