@@ -73,10 +73,12 @@ struct Transfer<double> {
         pl::step_source(j, al, S, ds, inr3, A, dtau);
     }
     // frequencies nu_obs[0 .. cnt) of up to G (entries g >= cnt are left untouched)
+    // (nothing for a sample that does not contribute, see `live`)
     template <int G>
     __device__ inline void contributions(const TraceParams& p, const double* nu_obs, int cnt, double* A,
                                          double* dtau) const
     {
+        if (!live) return;
 #pragma unroll
         for (int g = 0; g < G; ++g)
             if (g < cnt) contribution(p, nu_obs[g], A[g], dtau[g]);
@@ -123,13 +125,15 @@ struct Transfer<float> {
         contributions<1>(p, &nu_obs, 1, &A, &dtau);
     }
     // Frequencies nu_obs[0 .. cnt) of up to G at once, written without branches so that the G
-    // dependency chains interleave; entries g >= cnt, and frequencies whose emission is below
-    // exp(-1e8), are left untouched.
+    // dependency chains interleave; entries g >= cnt, frequencies whose emission is below
+    // exp(-1e8), and every entry of a sample that does not emit or contribute (`live`), are
+    // left untouched.
     template <int G>
     __device__ inline void contributions(const TraceParams& p, const double* nu_obs, int cnt, double* A,
                                          double* dtau) const
     {
         if (p.closure == CL_CONST) {
+            if (!live) return;
             const float j = (float)p.const_j, al = (float)p.const_alpha;
             float Af, dtf;
             pl::step_source(j, al, al > 0.0f ? j / al : 0.0f, ds, inr3, Af, dtf);
@@ -142,13 +146,14 @@ struct Transfer<float> {
             }
             return;
         }
-        if (!emits) return;
+        // a sample that does not emit goes through the same instructions, its results discarded
+        const bool on = emits && live;
         bool ok[G];
         double tt[G], An[G], Dt[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const double X = nu_obs[g] * nr_inv_nus;
-            ok[g] = g < cnt && X < 1e24;   // beyond, exp(-X^1/3) < exp(-1e8): no emission, no absorption
+            ok[g] = on && g < cnt && X < 1e24;   // beyond, exp(-X^1/3) < exp(-1e8): no emission, no absorption
             tt[g] = rt::cbrt_refined(ok[g] ? X : 1.0);
         }
 #pragma unroll
@@ -374,6 +379,7 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
     bool zamo = false;
     Transfer<TT> tr;
     tr.emits = false;
+    tr.live = false;
     if (has) {
         const DevGrid& G = p.grids[li.grid];
         const double y[8] = {q[0], q[1], q[2], q[3], q[4], q[5], 0.0, q[6]};
@@ -381,7 +387,8 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
         zamo = pl::fluid_frame(li.a, li.a * li.a, p.M, y, q[8], q[9], fl[3], &nr, &cb);
         // a non-positive fluid-frame frequency has no defined emission (see eval_sample): the
         // transfer stays non-emitting and the sample adds nothing
-        if (nr > 0.0) tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
+        tr.live = nr > 0.0;
+        if (tr.live) tr.setup(p, fl, nr, cb, nr * q[7] * p.length_unit);
     }
     c_zamo += __popcll(__ballot(zamo));
     const double nuc = pl::NUC_PER_GAUSS * fl[2];
@@ -677,19 +684,21 @@ trace_kernel(TraceParams p)
                     constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
                     int f = f0;
                     for (; f + G <= f1; f += G) {
-                        double nu[G], A[G], dt[G];
+                        double nu[G], A[G], dt[G], t0[G];
+                        TT att[G];   // formed before the contributions, so that the chains overlap
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
                             nu[g] = p.nu[li.nu_base + f + g];
                             A[g] = 0.0;
                             dt[g] = 0.0;
+                            t0[g] = Tr[f + g];
+                            att[g] = attenuation<TT>(t0[g]);
                         }
-                        if (tr.live) tr.template contributions<G>(p, nu, G, A, dt);
+                        tr.template contributions<G>(p, nu, G, A, dt);
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
-                            const double t0 = Tr[f + g];
-                            Ir[f + g] = Ir[f + g] + (double)attenuation<TT>(t0) * A[g];
-                            const double t1 = t0 + dt[g];
+                            Ir[f + g] = Ir[f + g] + (double)att[g] * A[g];
+                            const double t1 = t0[g] + dt[g];
                             Tr[f + g] = t1;
                             tmin = ::fmin(tmin, t1);
                             dtmax = ::fmax(dtmax, dt[g]);
@@ -697,7 +706,8 @@ trace_kernel(TraceParams p)
                     }
                     for (; f < f1; ++f) {
                         double A = 0.0, dt = 0.0;
-                        if (tr.live) tr.contribution(p, p.nu[li.nu_base + f], A, dt);
+                        const double nu1 = p.nu[li.nu_base + f];
+                        tr.template contributions<1>(p, &nu1, 1, &A, &dt);
                         const double t0 = Tr[f];
                         Ir[f] = Ir[f] + (double)attenuation<TT>(t0) * A;
                         const double t1 = t0 + dt;
@@ -759,7 +769,7 @@ trace_kernel(TraceParams p)
                             A[g] = 0.0;
                             dt[g] = 0.0;
                         }
-                        if (tr.live) tr.template contributions<G>(p, nu, cnt, A, dt);
+                        tr.template contributions<G>(p, nu, cnt, A, dt);
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
                             if (g < cnt) {
