@@ -113,23 +113,41 @@ def time_spectrum(ctx, R, cam, gh, nu, opts, images, flux, steps, warmup):
 def spectrum_section(args, R, S, ctx, prec):
     """The spectrum camera: 256^2 pixels, a = 0.9375, i = 60 deg, 24 log-spaced frequencies
     1e9..1e16 Hz on shared geodesics; fast light (the snapshot at the frame time) and slow light
-    (64 modulated float32 256^2 snapshots interpolated along each ray); graph launch."""
+    (64 modulated float32 256^2 snapshots interpolated along each ray); the launch plan chosen by
+    the library's autotuner for each form, then graph launch.  With a trained network, the fast-
+    light spectrum also with the learned closure, and its flux error against the exact one."""
+    import numpy as np
     import torch
     cam, grid, nu = S.slow_light_set()
     gh = ctx.upload_grid(grid)
     images = torch.empty(len(nu) * cam.nx * cam.ny, dtype=torch.float64, device="cuda")
     flux = torch.empty(len(nu), dtype=torch.float64, device="cuda")
     out = {"config": {"workload": "spectrum camera 256x256, a 0.9375, i 60 deg, 24 frequencies 1e9..1e16 Hz, "
-                                  "64 float32 256^2 snapshots (m=1..4 modulation, amplitude 0.2)",
+                                  "64 float32 256^2 snapshots (m=1..4 modulation, amplitude 0.2), autotuned plan",
                       "n_nu": len(nu)}}
-    for name, slow in (("fast_light", 0), ("slow_light", 1)):
-        opts = R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, slow_light=slow)
+    forms = [("fast_light", 0, R.CLOSURE_EXACT), ("slow_light", 1, R.CLOSURE_EXACT)]
+    if args.mlp_ready:
+        forms.append(("fast_light_mlp", 0, R.CLOSURE_MLP))
+    fluxes = {}
+    for name, slow, cl in forms:
+        tune = R.default_opts(transfer_prec=prec, slow_light=slow, closure=cl)
+        plan, _ = R.autotune_batch(ctx, [cam], [gh], nu, tune, reps=1)
+        opts = R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, slow_light=slow,
+                              closure=cl)
         r = time_spectrum(ctx, R, cam, gh, nu, opts, images, flux, args.steps, args.warmup)
+        fluxes[name] = flux.cpu().numpy().copy()
         out[name] = {"ms_per_step": r["ms"], "kernel_ms": r["kernel_ms"],
                      "value": r["ray_steps"] / (r["ms"] * 1e-3), "unit": "ray-steps/s",
                      "spectra_per_s": 1e3 / r["ms"], "ray_steps_per_step": r["ray_steps"],
-                     "samples_per_step": r["samples"],
+                     "samples_per_step": r["samples"], "plan": plan.as_dict(),
                      "roofline": roofline_of(R, r, r["kernel_ms"], prec == R.F64, len(nu))}
+    if "fast_light_mlp" in fluxes:
+        ex = fluxes["fast_light"]
+        rel = np.abs(fluxes["fast_light_mlp"] / np.where(ex != 0, ex, 1.0) - 1.0)
+        out["fast_light_mlp"]["max_rel_flux_err_vs_exact"] = float(rel.max())
+        out["fast_light_mlp"]["rel_flux_err_per_frequency"] = [float(x) for x in rel]
+        out["fast_light"]["flux_jy"] = [float(x) for x in ex]
+        out["fast_light_mlp"]["time_vs_exact"] = out["fast_light_mlp"]["kernel_ms"] / out["fast_light"]["kernel_ms"]
     ctx.release_grid(gh)
     return out
 

@@ -45,6 +45,19 @@ struct Transfer<double> {
     double ne, the, bf, sinb, ln_k2, ds, inr3, nr;
     bool emits;
     bool live;   // the sample contributes (a positive fluid-frame frequency)
+    // the state as doubles (kept in LDS between the phases of a frequency-parallel round)
+    static constexpr int WORDS = 9;
+    __device__ inline void to_words(double* w) const
+    {
+        w[0] = ne; w[1] = the; w[2] = bf; w[3] = sinb; w[4] = ln_k2; w[5] = ds; w[6] = inr3; w[7] = nr;
+        w[8] = __hiloint2double((int)live, (int)emits);
+    }
+    __device__ inline void from_words(const double* w)
+    {
+        ne = w[0]; the = w[1]; bf = w[2]; sinb = w[3]; ln_k2 = w[4]; ds = w[5]; inr3 = w[6]; nr = w[7];
+        emits = __double2loint(w[8]) != 0;
+        live = __double2hiint(w[8]) != 0;
+    }
     __device__ inline void setup(const TraceParams& p, const double fl[4], double nr_, double cosb, double dsv)
     {
         ne = fl[0]; the = fl[1]; bf = fl[2];
@@ -102,6 +115,28 @@ struct Transfer<float> {
     double nr;
     bool emits;
     bool live;   // the sample contributes (a positive fluid-frame frequency)
+    // the state as doubles, floats in pairs (kept in LDS between the phases of a
+    // frequency-parallel round)
+    static constexpr int WORDS = 7;
+    __device__ static inline double pack(float a, float b)
+    {
+        return __hiloint2double((int)__float_as_uint(b), (int)__float_as_uint(a));
+    }
+    __device__ inline void to_words(double* w) const
+    {
+        w[0] = pack(ne, the); w[1] = pack(inv_the, nu_s); w[2] = pack(ds, inr3);
+        w[3] = ln_k2; w[4] = nr_inv_nus; w[5] = nr;
+        w[6] = __hiloint2double((int)live, (int)emits);
+    }
+    __device__ inline void from_words(const double* w)
+    {
+        ne = __uint_as_float((unsigned)__double2loint(w[0])); the = __uint_as_float((unsigned)__double2hiint(w[0]));
+        inv_the = __uint_as_float((unsigned)__double2loint(w[1])); nu_s = __uint_as_float((unsigned)__double2hiint(w[1]));
+        ds = __uint_as_float((unsigned)__double2loint(w[2])); inr3 = __uint_as_float((unsigned)__double2hiint(w[2]));
+        ln_k2 = w[3]; nr_inv_nus = w[4]; nr = w[5];
+        emits = __double2loint(w[6]) != 0;
+        live = __double2hiint(w[6]) != 0;
+    }
     __device__ inline void setup(const TraceParams& p, const double fl[4], double nr_, double cosb, double dsv)
     {
         ne = (float)fl[0];
@@ -303,29 +338,25 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
 }
 
 // A sample's transfer set-up kept in LDS between the two phases of a frequency-parallel round:
-// the bytes of Transfer<TT> in the sample's queue slot, in the fields the evaluation no longer
-// needs (every field but the step length, which the fold still reads).
+// Transfer<TT>'s words in the sample's queue slot, in the fields the evaluation no longer needs
+// (every field but the step length, which the fold still reads).
 constexpr int SETUP_FIELDS[9] = {0, 1, 2, 3, 4, 5, 6, 8, 9};
-template <class TT>
-struct SetupWords {
-    static constexpr int N = (int)((sizeof(Transfer<TT>) + 7) / 8);
-    static_assert(N <= 9, "the transfer set-up fits the sample's free queue fields");
-};
 template <class TT, int SLOTS>
 __device__ inline void store_setup(double* fields, int s, const Transfer<TT>& tr)
 {
-    double w[SetupWords<TT>::N];
-    __builtin_memcpy(w, &tr, sizeof(Transfer<TT>));
+    static_assert(Transfer<TT>::WORDS <= 9, "the transfer set-up fits the sample's free queue fields");
+    double w[Transfer<TT>::WORDS];
+    tr.to_words(w);
 #pragma unroll
-    for (int k = 0; k < SetupWords<TT>::N; ++k) fields[SETUP_FIELDS[k] * SLOTS + s] = w[k];
+    for (int k = 0; k < Transfer<TT>::WORDS; ++k) fields[SETUP_FIELDS[k] * SLOTS + s] = w[k];
 }
 template <class TT, int SLOTS>
 __device__ inline void load_setup(const double* fields, int s, Transfer<TT>& tr)
 {
-    double w[SetupWords<TT>::N];
+    double w[Transfer<TT>::WORDS];
 #pragma unroll
-    for (int k = 0; k < SetupWords<TT>::N; ++k) w[k] = fields[SETUP_FIELDS[k] * SLOTS + s];
-    __builtin_memcpy(&tr, w, sizeof(Transfer<TT>));
+    for (int k = 0; k < Transfer<TT>::WORDS; ++k) w[k] = fields[SETUP_FIELDS[k] * SLOTS + s];
+    tr.from_words(w);
 }
 
 // The learned closure's step contribution in FP32 transfer, by the scheme of Transfer<float>: the
