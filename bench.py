@@ -193,7 +193,7 @@ def uneven_batch_section(args, R, S, ctx, prec):
                      "roofline": roofline_of(R, r, r["kernel_ms"], prec == R.F64, len(nu))}
         if name == "mlp":
             out[name]["exact_fallback_fraction"] = r["fallback"] / max(r["samples"] * len(nu), 1.0)
-            out[name]["dropped_below_float_fraction"] = r["dropped"] / max(r["samples"] * len(nu), 1.0)
+            out[name]["dropped_exact_zero_fraction"] = r["dropped"] / max(r["samples"] * len(nu), 1.0)
     if "mlp" in fluxes:
         rel = fluxes["mlp"] / fluxes["exact"] - 1.0
         out["mlp"]["max_abs_flux_rel_err"] = float(np.abs(rel).max())
@@ -369,7 +369,7 @@ def main():
                       "max_abs_flux_rel_err": float(np.abs(rel).max()),
                       "flux_rel_err_per_image": [float(x) for x in rel],
                       "exact_fallback_fraction": mlp["fallback"] / max(mlp["samples"], 1.0),
-                      "dropped_below_float_fraction": mlp["dropped"] / max(mlp["samples"], 1.0),
+                      "dropped_exact_zero_fraction": mlp["dropped"] / max(mlp["samples"], 1.0),
                       "form": "split BF16 MFMA, FP32 accumulate",
                       "training": {"steps": rep.steps, "train_ms": rep.train_ms,
                                    "val_rms_ln_j": rep.val_rms[0], "val_rms_ln_alpha": rep.val_rms[1]}}

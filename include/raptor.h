@@ -163,9 +163,10 @@ typedef struct {
 /* Counters of the last trace call.  ray_steps counts accepted steps, samples the plasma
  * samples evaluated, n_mlp_fallback the sample-frequencies that the learned closure handed to
  * the exact closure (inputs outside its box), n_opaque the rays stopped by the optical-depth
- * cut-off, n_mlp_dropped the sample-frequencies outside the learned closure's box whose emission
- * it dropped because the cut-off factor exp(-X^1/3) of thermal synchrotron emission lies below
- * the float range there (X^1/3 > 88, X = nu / nu_s). */
+ * cut-off, n_mlp_dropped the sample-frequencies outside the learned closure's box that it skipped
+ * because the exact closure gives exactly zero there: the factor exp(-(X^1/3 + ln K2(1/Theta_e)))
+ * of thermal synchrotron emission lies below the smallest double (X^1/3 + ln K2 > 746,
+ * X = nu / nu_s). */
 typedef struct {
     uint64_t rays, ray_steps, samples, n_horizon, n_escaped, n_maxstep, n_pole, n_numeric,
              n_mlp_fallback, n_zamo_fallback;
@@ -274,7 +275,7 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
 /* ------------------------------------------------------------------------------------------
  * Learned closure (an addition to the paper's method).  A 3 -> 64 -> 64 -> 64 -> 64 -> 2 SiLU
  * network maps (ln(nu/nu_c), ln Theta_e, cos theta_B), normalised to [-1, 1] over the box
- * nu/nu_c in [1e-2, 1e6], Theta_e in [0.1, 100], |cos theta_B| <= 0.999, to
+ * nu/nu_c in [1e-2, 1e8], Theta_e in [0.1, 100], |cos theta_B| <= 0.999, to
  * ln j_hat = ln(j / (n_e nu_c J0)) and ln alpha_hat = ln j_hat - 2 ln(nu/nu_c) - ln Theta_e,
  * J0 = sqrt2 pi e^2 / (3c), where alpha_hat is the Rayleigh-Jeans absorption in units of
  * n_e J0 / (2 m_e nu_c).  The network's two outputs are the standardised values of
@@ -294,7 +295,7 @@ enum { RAPTOR_MLP_PARAMS = 12866 };
 typedef struct {
     int64_t n_train;             /* training samples generated on the device (default 1e7) */
     int64_t n_val;               /* validation samples (default 1e5) */
-    int32_t epochs;              /* passes over the training samples (default 150) */
+    int32_t epochs;              /* passes over the training samples (default 180) */
     int32_t batch;               /* samples per Adam step, a multiple of 64 (default 6144) */
     float lr, lr_final;          /* Adam step size, cosine-decayed from lr to lr_final (defaults 8e-3, 2e-5) */
     float beta1, beta2, adam_eps, weight_decay;

@@ -36,9 +36,9 @@ constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 44
 // BF16 copies padded to multiples of 16: W[out_pad][in_pad] and WT[in_pad][out_pad]
 constexpr int PW1 = 0, PW2 = 1024, PW3 = 5120, PW4 = 9216, PW5 = 13312, PW_TOTAL = 14336;
 
-// training box (ln(nu/nu_c) in [ln 1e-2, ln 1e6], ln Theta_e in [ln 0.1, ln 100], |cos| <= 0.999)
+// training box (ln(nu/nu_c) in [ln 1e-2, ln 1e8], ln Theta_e in [ln 0.1, ln 100], |cos| <= 0.999)
 // and standardisation of the two outputs
-constexpr float LX_LO = -4.605170185988091f, LX_HI = 13.815510557964274f;
+constexpr float LX_LO = -4.605170185988091f, LX_HI = 18.420680743952367f;
 constexpr float LT_LO = -2.302585092994046f, LT_HI = 4.605170185988092f;
 constexpr float CB_LO = -0.999f, CB_HI = 0.999f;
 constexpr float MU_J = 4.0f, SIGMA_J = 6.0f, MU_A = -6.5f, SIGMA_A = 9.0f;

@@ -113,7 +113,7 @@ raptor_status raptor_mlp_default_cfg(raptor_mlp_train_cfg* c)
     std::memset(c, 0, sizeof *c);
     c->n_train = 10000000;
     c->n_val = 100000;
-    c->epochs = 150;
+    c->epochs = 180;
     c->batch = 6144;
     c->lr = 8e-3f;
     c->lr_final = 2e-5f;

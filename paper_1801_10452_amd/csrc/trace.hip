@@ -393,12 +393,12 @@ __device__ inline void mlp_contribution_f32(const Transfer<float>& tr, float y0,
 
 // Learned-closure variant of eval_sample for one round: every lane of the wave takes part in the
 // network evaluations (one per frequency); lanes without a sample feed zeros.  Samples whose
-// closure inputs leave the training box use the exact closure, except where the emission's
-// cut-off factor exp(-X^1/3) lies below the float range (X^1/3 > 88, X > 88^3): there emission
-// and absorption (j / B_nu) are dropped, which changes no flux at any measurable level (such a
-// sample's j is below 1e-38 of its prefactor) and spares the fallback the samples of the dilute,
-// weakly magnetised outer flow, where nu/nu_c exceeds the box's 1e6.
-constexpr double MLP_DROP_X = 88.0 * 88.0 * 88.0;
+// closure inputs leave the training box use the exact closure, except where the exact closure
+// itself gives exactly zero: where X^1/3 + ln K2(1/Theta_e) exceeds MLP_ZERO_EXP, the factor
+// exp(-(X^1/3 + ln K2)) lies below the smallest double, so j and alpha vanish in both transfer
+// precisions (the FP32 transfer's power of two 2^-n has n >= 1076 there).  Those samples are
+// skipped (counted as dropped) at no change to any result.
+constexpr double MLP_ZERO_EXP = 746.0;
 
 template <int NNU, class TT>
 __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char* lds_net, bool has, const double* q,
@@ -434,7 +434,9 @@ __device__ inline void eval_round_mlp(const TraceParams& p, const unsigned char*
         const double nu = act ? p.nu[li.nu_base + f] * nr : nuc;
         const float lx = (float)rt::log_pos(nu / nuc);
         const bool inb = act && tr.emits && mlp::in_box(lx, lth, (float)cb);
-        const bool drop = act && tr.emits && !inb && nu > MLP_DROP_X * nus;
+        // X^1/3 + ln K2 > MLP_ZERO_EXP  <=>  X > t_lim^3, t_lim = MLP_ZERO_EXP - ln K2 (X^1/3 >= 0)
+        const double t_lim = MLP_ZERO_EXP - tr.ln_k2;
+        const bool drop = act && tr.emits && !inb && (t_lim <= 0.0 || nu > t_lim * t_lim * t_lim * nus);
         c_fallback += __popcll(__ballot(act && tr.emits && !inb && !drop));
         c_dropped += __popcll(__ballot(drop));
         const float x0 = inb ? mlp::norm_lx(lx) : 0.0f, x1 = inb ? mlp::norm_lt(lth) : 0.0f,

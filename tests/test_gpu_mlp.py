@@ -226,7 +226,7 @@ def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
     st_m, st_x = res["mlp_split"][1], res["exact"][1]
     fb = st_m.n_mlp_fallback / st_m.samples
     print(f"[mlp gain] learned / exact kernel time {st_m.kernel_ms / st_x.kernel_ms:.2f}; exact fallback "
-          f"{fb:.4f} of the sample-frequencies, dropped (X^1/3 > 88) {st_m.n_mlp_dropped / st_m.samples:.4f}",
+          f"{fb:.4f} of the sample-frequencies, dropped (exact closure zero) {st_m.n_mlp_dropped / st_m.samples:.4f}",
           flush=True)
     assert e_mlp.max() <= 1e-3
     assert e_mlp.max() < e_k2.min()
