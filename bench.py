@@ -61,6 +61,11 @@ def oracle_sample(sets, oo, threads, budget_s):
     return steps, rays, time.perf_counter() - t0
 
 
+def progress(msg):
+    """One line on stderr per finished part of the run (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(sets, opts_gpu, budget_s=15.0, budget_1core_s=8.0):
     """The oracle on this host's cores, then on one core, over bounded strided pixel samples of
     the same workload: ray-steps per second and the equivalent 512^2 images per second."""
@@ -130,6 +135,7 @@ def spectrum_section(args, R, S, ctx, prec):
         forms.append(("fast_light_mlp", 0, R.CLOSURE_MLP))
     fluxes = {}
     for name, slow, cl in forms:
+        progress(f"spectrum {name}: autotuning, then timing")
         tune = R.default_opts(transfer_prec=prec, slow_light=slow, closure=cl)
         plan, _ = R.autotune_batch(ctx, [cam], [gh], nu, tune, reps=1)
         opts = R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, slow_light=slow,
@@ -177,6 +183,7 @@ def uneven_batch_section(args, R, S, ctx, prec):
         forms.append(("mlp", R.CLOSURE_MLP))
     fluxes = {}
     for name, cl in forms:
+        progress(f"uneven batch {name}: autotuning, then timing")
         tune = R.default_opts(transfer_prec=prec, closure=cl)
         t0 = time.perf_counter()
         plan, tuned_ms = R.autotune_batch(ctx, cams, grids, nu, tune, reps=1)
@@ -310,6 +317,7 @@ def main():
     nu = [S.NU_230]
     torch.cuda.synchronize()
 
+    progress("production batch: timing the exact closure")
     plain = time_form(ctx, R, cams, grids, nu, R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=launch),
                       images, flux, args.steps, args.warmup)
     ms = plain["ms"]
@@ -358,7 +366,9 @@ def main():
         cfg = R.mlp_default_cfg()
         if args.mlp_epochs > 0:
             cfg.epochs = args.mlp_epochs
+        progress("training the learned closure")
         rep = R.mlp_train(ctx, cfg)
+        progress(f"trained in {rep.train_ms / 1e3:.1f} s; timing the production batch with the network")
         mlp = time_form(ctx, R, cams, grids, nu,
                         R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=launch, closure=R.CLOSURE_MLP),
                         images, flux, args.steps, args.warmup)
@@ -375,9 +385,12 @@ def main():
                                    "val_rms_ln_j": rep.val_rms[0], "val_rms_ln_alpha": rep.val_rms[1]}}
         args.mlp_ready = True
     if not args.no_extra:
+        progress("spectrum camera")
         out["spectrum"] = spectrum_section(args, R, S, ctx, prec)
+        progress("uneven batch")
         out["uneven_batch"] = uneven_batch_section(args, R, S, ctx, prec)
     if not args.no_cpu_baseline:
+        progress("CPU baseline (the oracle)")
         out["cpu_baseline"] = cpu_baseline(sets, R.default_opts(transfer_prec=prec))
     print(json.dumps(out), flush=True)
     ctx.close()
