@@ -87,7 +87,7 @@ struct Transfer<double> {
     }
     // frequencies nu_obs[0 .. cnt) of up to G (entries g >= cnt are left untouched)
     // (nothing for a sample that does not contribute, see `live`)
-    template <int G>
+    template <int G, bool BRANCHES = (G == 1)>
     __device__ inline void contributions(const TraceParams& p, const double* nu_obs, int cnt, double* A,
                                          double* dtau) const
     {
@@ -155,15 +155,44 @@ struct Transfer<float> {
         if (emits && p.closure != CL_CONST)
             ln_k2 = (p.closure == CL_K2_PAPER) ? rt::log_pos(2.0 * fl[1] * fl[1]) : pl::ln_k2_theta(p.k2, fl[1]);
     }
+    // One frequency's coefficients from tt = X^1/3 (X = nu_obs nu_r / nu_s): the power of two
+    // 2^-n of exp(-(ln K2 + tt)) = 2^-n 2^-f, the float mantissas of j (jm, j = jm 2^-n) and of
+    // the source S = B_nu, and the step's optical depth dt in double.
+    struct Terms {
+        double scale, dt;
+        float jm, S;
+    };
+    __device__ inline Terms terms(double tt, double nu_obs) const
+    {
+        // exp(-(ln K2 + tt)) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in
+        // double too, and the exponent is kept above -1000 so that the scale stays finite
+        const double z = ::fmax(::fmin((tt + ln_k2) * 1.4426950408889634, 1100.0), -1000.0);
+        const double n = __builtin_rint(z);
+        const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
+        Terms T;
+        T.scale = __builtin_ldexp(1.0, -(int)n);
+        const float t = (float)tt;
+        const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
+        T.jm = 1.1396857174835936e-29f * ne * nu_s * t * tc * tc * em;   // j = jm 2^-n
+        const float nuf = (float)(nu_obs * nr);
+        const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
+        const float q3 = q * q * q;                               // 2 h nu^3 / c^2
+        const float em1 = rt::expm1_f((float)pl::H_OVER_MEC2 * nuf * inv_the);
+        T.S = q3 * rt::rcpf_nr(em1);                              // B_nu
+        const float dtm = T.jm * em1 * rt::rcpf_nr(q3) * ds;      // dtau = dtm 2^-n
+        T.dt = (double)dtm * T.scale;
+        return T;
+    }
     __device__ inline void contribution(const TraceParams& p, double nu_obs, double& A, double& dtau) const
     {
         contributions<1>(p, &nu_obs, 1, &A, &dtau);
     }
-    // Frequencies nu_obs[0 .. cnt) of up to G at once, written without branches so that the G
-    // dependency chains interleave; entries g >= cnt, frequencies whose emission is below
+    // Frequencies nu_obs[0 .. cnt) of up to G at once, written without branches (unless G = 1
+    // and BRANCHES) so that the G dependency chains interleave, and so that consecutive calls in
+    // a loop stay free of branches; entries g >= cnt, frequencies whose emission is below
     // exp(-1e8), and every entry of a sample that does not emit or contribute (`live`), are
     // left untouched.
-    template <int G>
+    template <int G, bool BRANCHES = (G == 1)>
     __device__ inline void contributions(const TraceParams& p, const double* nu_obs, int cnt, double* A,
                                          double* dtau) const
     {
@@ -181,6 +210,19 @@ struct Transfer<float> {
             }
             return;
         }
+        if constexpr (G == 1 && BRANCHES) {
+            // one frequency: branches skip the work that the selects below would only discard
+            if (!(emits && live) || cnt < 1) return;
+            const double X = nu_obs[0] * nr_inv_nus;
+            if (!(X < 1e24)) return;   // exp(-X^1/3) < exp(-1e8): no emission, no absorption
+            const Terms T = terms(rt::cbrt_refined(X), nu_obs[0]);
+            dtau[0] = T.dt;
+            if (T.dt > 1e-8)
+                A[0] = (double)(T.S * -rt::expm1_f(-(float)T.dt) * inr3);
+            else
+                A[0] = (double)(T.jm * ds * inr3) * T.scale;   // S dtau = j ds to float precision
+            return;
+        }
         // a sample that does not emit goes through the same instructions, its results discarded
         const bool on = emits && live;
         bool ok[G];
@@ -193,27 +235,12 @@ struct Transfer<float> {
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            // exp(-(ln K2 + tt)) = 2^-n 2^-f, |f| <= 1/2; beyond 2^-1100 the emission is zero in
-            // double too, and the exponent is kept above -1000 so that the scale stays finite
-            const double z = ::fmax(::fmin((tt[g] + ln_k2) * 1.4426950408889634, 1100.0), -1000.0);
-            const double n = __builtin_rint(z);
-            const float em = __builtin_amdgcn_exp2f(-(float)(z - n));
-            const double scale = __builtin_ldexp(1.0, -(int)n);
-            const float t = (float)tt[g];
-            const float tc = t + 1.8877486253633868f;                 // 2^(11/12)
-            const float jm = 1.1396857174835936e-29f * ne * nu_s * t * tc * tc * em;   // j = jm 2^-n
-            const float nuf = (float)(nu_obs[g] * nr);
-            const float q = nuf * 2.45215662654257e-16f;              // nu (2h/c^2)^(1/3)
-            const float q3 = q * q * q;                               // 2 h nu^3 / c^2
-            const float em1 = rt::expm1_f((float)pl::H_OVER_MEC2 * nuf * inv_the);
-            const float S = q3 * rt::rcpf_nr(em1);                    // B_nu
-            const float dtm = jm * em1 * rt::rcpf_nr(q3) * ds;        // dtau = dtm 2^-n
-            const double dt = (double)dtm * scale;
+            const Terms T = terms(tt[g], nu_obs[g]);
             // 1 - exp(-dtau) = dtau (1 - dtau/2 + ...): below 1e-8, S dtau = j ds to float precision
-            const double a_thick = (double)(S * -rt::expm1_f(-(float)dt) * inr3);
-            const double a_thin = (double)(jm * ds * inr3) * scale;
-            An[g] = dt > 1e-8 ? a_thick : a_thin;
-            Dt[g] = dt;
+            const double a_thick = (double)(T.S * -rt::expm1_f(-(float)T.dt) * inr3);
+            const double a_thin = (double)(T.jm * ds * inr3) * T.scale;
+            An[g] = T.dt > 1e-8 ? a_thick : a_thin;
+            Dt[g] = T.dt;
         }
         // The G results are consumed here, unconditionally, by empty asm statements: without
         // that the compiler sinks each chain into a branch on ok[g], one after another, and the
@@ -737,10 +764,10 @@ trace_kernel(TraceParams p)
                             dtmax = ::fmax(dtmax, dt[g]);
                         }
                     }
-                    for (; f < f1; ++f) {
+                    for (; f < f1; ++f) {   // the rest one at a time, in the branch-free form
                         double A = 0.0, dt = 0.0;
                         const double nu1 = p.nu[li.nu_base + f];
-                        tr.template contributions<1>(p, &nu1, 1, &A, &dt);
+                        tr.template contributions<1, false>(p, &nu1, 1, &A, &dt);
                         const double t0 = Tr[f];
                         Ir[f] = Ir[f] + (double)attenuation<TT>(t0) * A;
                         const double t1 = t0 + dt;
