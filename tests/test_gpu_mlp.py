@@ -268,6 +268,36 @@ def test_trained_network_vlbi_and_slow_light_against_oracle_exact(R, ctx, orc):
     assert worst_o <= 1e-3 and worst_g <= 1e-3
 
 
+def test_trained_network_spectrum_every_frequency(R, ctx, orc):
+    """The trained network on a 48^2 spectrum camera (a = 0.9375, i = 60 deg, float32 128^2 grid)
+    at the 24 log-spaced frequencies 1e9..1e16 Hz: every frequency's flux within 1e-3 of the GPU
+    exact closure's and of the oracle's, and nonzero wherever the exact flux is.  At the top
+    frequencies every sample lies outside the training box, so those fluxes come from the
+    exact-closure fallback; only samples whose exact emission is exactly zero may be skipped."""
+    if not getattr(ctx, "_trained", False):
+        R.mlp_init(ctx)
+        R.mlp_train(ctx)
+        ctx._trained = True
+    from tests.gpu_common import oracle_opts
+    nu = S.spectrum_freqs()
+    cam = S.Camera(spin=0.9375, incl_deg=60.0, nx=48, ny=48)
+    g = S.make_grid(128, 128, a_gen=0.9375, dtype=np.float32)
+    gh = ctx.upload_grid(g)
+    _, fm, sm = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32, closure=R.CLOSURE_MLP))
+    _, fx, _ = ctx.trace_spectrum(cam, gh, nu, R.default_opts(transfer_prec=R.F32))
+    ctx.release_grid(gh)
+    _, fo, _ = orc.trace_image(cam, orc.GridHandle(g), oracle_opts(orc, R.default_opts()), nu)
+    fm, fx, fo = np.asarray(fm), np.asarray(fx), np.asarray(fo)
+    m = (fx > 0) & (fo > 0)
+    assert m.sum() >= 20
+    eg = np.abs(fm[m] / fx[m] - 1)
+    eo = np.abs(fm[m] / fo[m] - 1)
+    print(f"[mlp spectrum] {m.sum()} frequencies with flux; worst |dF/F| vs gpu exact {eg.max():.3e}, vs oracle "
+          f"{eo.max():.3e}; fallback {sm.n_mlp_fallback}/{sm.samples * len(nu)} skipped {sm.n_mlp_dropped}", flush=True)
+    assert (fm[m] > 0).all()
+    assert eg.max() <= 1e-3 and eo.max() <= 1e-3
+
+
 def test_trained_network_uneven_batch_autotuned_graph(R, ctx):
     """The uneven batch (256 images of 64^2..512^2, four VLBI frequencies) with the trained
     network, in its timed form: autotuned plan for the learned closure, graph-captured launch
