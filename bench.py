@@ -261,6 +261,7 @@ def spectrum_slow_light(args):
     ctx = R.Context(0, use_torch_stream=True)
     gh = ctx.upload_grid(grid)
     opts = R.default_opts(transfer_prec=R.F32, slow_light=1)
+    plan, _ = R.autotune_batch(ctx, [cam], [gh], nu, opts, reps=1)   # the plan the benchmark times
     for _ in range(args.warmup):
         ctx.trace_spectrum(cam, gh, nu, opts)
     ms, st = [], None
@@ -271,7 +272,7 @@ def spectrum_slow_light(args):
     # two snapshots x four cells x 16 bytes per sample
     gather = st.samples * 2 * 4 * 16
     print(json.dumps({"workload": "spectrum 256x256, 24 frequencies, slow light (64 float32 256^2 snapshots)",
-                      "kernel_ms": k, "ray_steps": st.ray_steps, "samples": st.samples,
+                      "plan": plan.as_dict(), "kernel_ms": k, "ray_steps": st.ray_steps, "samples": st.samples,
                       "ray_steps_per_s": st.ray_steps / k * 1e3, "gather_bytes_per_launch": gather,
                       "gather_GBps": gather / k * 1e-6, "grid_bytes": int(grid.cells.nbytes)}), flush=True)
 
