@@ -246,7 +246,15 @@ typedef struct {
     int32_t min_waves_per_simd;  /* 1, 2 or 3: the kernel variant compiled for at least that many
                                     waves per SIMD (register cap 512, 256 or 168); the 3-wave
                                     variant sizes its LDS sample queue for 12 waves per CU */
-    int32_t reserved[3];
+    int32_t rays_per_wave;       /* 0 or 64 (default), 32 or 16: rays per tile and per wave.  Below
+                                    64 only for the variants whose sample queue holds one sample per
+                                    lane (several frequencies, exact or paper closure); the lanes
+                                    without a ray then only take part in the frequency-parallel
+                                    sample rounds, and the LDS of a wave shrinks with the rays, so
+                                    more waves fit: for launches with fewer tiles than wave slots.
+                                    Elsewhere, and as installed, 64; a tile wider than the rays is
+                                    narrowed to them */
+    int32_t reserved[2];
 } raptor_plan;
 
 /* Current plan for (n_nu, transfer_prec, closure) (the default plan if none was set or tuned:

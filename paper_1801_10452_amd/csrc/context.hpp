@@ -66,7 +66,7 @@ struct NoAllocHost {
 };
 
 struct LaunchPlan {
-    raptor_plan p{256, 0, 1, 8, 2, {0, 0, 0}};
+    raptor_plan p{256, 0, 1, 8, 2, 64, {0, 0}};
     int blocks = 0;   // resolved work-group count
 };
 

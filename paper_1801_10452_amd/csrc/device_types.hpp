@@ -62,7 +62,10 @@ struct TraceParams {
     K2Table k2;
     long long n_tiles;
     int n_jobs, max_steps, closure, slow_light, integrator, pad;
-    int refill_threshold, tile_shift;   // tile width = 1 << tile_shift pixels, height 64 / width
+    int refill_threshold, tile_shift;   // tile width = 1 << tile_shift pixels, height rays / width
+    // rays per tile and per wave (64, or 32 / 16 for the kernels whose sample queue holds one
+    // sample per lane: the other lanes then only take part in the frequency-parallel rounds)
+    int rays_per_wave, rays_shift;
     double eps, M, length_unit, const_j, const_alpha, tau_cutoff;
     double tau_step;           // > 0: optical-depth-aware step (at most tau_step per step at the last sample)
     // learned closure (closure == CL_MLP): FP32 parameters and padded BF16 hi / lo weights

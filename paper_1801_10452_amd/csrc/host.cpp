@@ -147,9 +147,26 @@ raptor_status check_camera(raptor_ctx* ctx, const raptor_camera* c, const raptor
 bool plan_valid(const raptor_plan& p)
 {
     const bool tw = p.tile_width == 8 || p.tile_width == 16 || p.tile_width == 32 || p.tile_width == 64;
+    const bool rw = p.rays_per_wave == 0 || p.rays_per_wave == 16 || p.rays_per_wave == 32 || p.rays_per_wave == 64;
     return (p.threads == 64 || p.threads == 128 || p.threads == 256 || p.threads == 512) && p.blocks_per_cu >= 0 &&
-           p.blocks_per_cu <= 64 && p.refill_threshold >= 1 && p.refill_threshold <= 64 && tw &&
+           p.blocks_per_cu <= 64 && p.refill_threshold >= 1 && p.refill_threshold <= 64 && tw && rw &&
            (p.min_waves_per_simd >= 1 && p.min_waves_per_simd <= 3);
+}
+
+// Rays per wave and tile width a launch of this plan uses: fewer than 64 rays only where the
+// instantiation that runs (frequency class, precision, closure class, integrator) keeps one
+// sample per lane, and a tile no wider than the rays.
+struct Geometry {
+    int rays, tile_w;
+};
+Geometry launch_geometry(const raptor_plan& p, int n_nu, bool fp32, bool mlpc, int integ)
+{
+    Geometry g{64, p.tile_width};
+    if ((p.rays_per_wave == 16 || p.rays_per_wave == 32) &&
+        trace_kernel_one_slot(n_nu, fp32, p.min_waves_per_simd, mlpc, integ))
+        g.rays = p.rays_per_wave;
+    if (g.tile_w > g.rays) g.tile_w = g.rays;
+    return g;
 }
 
 int plan_key(int n_nu, bool fp32, bool mlpc)
@@ -169,16 +186,23 @@ raptor_status resolve_plan(raptor_ctx* ctx, int max_nu, bool fp32, LaunchPlan* p
                                       &max_threads),
               "reading kernel attributes");
     while (pl->p.threads > 64 && pl->p.threads > max_threads) pl->p.threads /= 2;
+    // rays per wave and tile width as the RK4 instantiation runs them (64 rays where it keeps
+    // more than one sample per lane)
+    const Geometry g = launch_geometry(pl->p, max_nu, fp32, mlpc, INTEG_RK4);
+    pl->p.rays_per_wave = g.rays;
+    pl->p.tile_width = g.tile_w;
+    auto lds = [&]() {
+        return trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4, g.rays);
+    };
     // the per-wave sample queue lives in LDS: shrink the work-group until it fits
-    while (pl->p.threads > 64 && trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4) > ctx->lds_per_block)
-        pl->p.threads /= 2;
-    if (trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4) > ctx->lds_per_block)
+    while (pl->p.threads > 64 && lds() > ctx->lds_per_block) pl->p.threads /= 2;
+    if (lds() > ctx->lds_per_block)
         return fail(ctx, RAPTOR_E_UNSUPPORTED, "the sample queue of one wave exceeds the LDS of a work-group");
     int per_cu = pl->p.blocks_per_cu;
     if (per_cu == 0) {
         RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                       &per_cu, trace_kernel_symbol(max_nu, fp32, pl->p.min_waves_per_simd, mlpc), pl->p.threads,
-                      trace_kernel_lds(max_nu, fp32, pl->p.min_waves_per_simd, pl->p.threads, mlpc, INTEG_RK4)),
+                      lds()),
                   "querying occupancy");
         per_cu = std::max(per_cu, 1);
     }
@@ -295,9 +319,9 @@ struct HostTables {
 };
 
 raptor_status fill_tables(raptor_ctx* ctx, const JobIn* in, int nj, int n_nu, const raptor_opts* o, int tile_w,
-                          HostTables* t)
+                          int rays, HostTables* t)
 {
-    const int tile_h = 64 / tile_w;
+    const int tile_h = rays / tile_w;
     const double M = o->metric_mass;
     const double Lu = kG * o->mass_msun * kMsun / (kC * kC);
     const double D = o->dist_pc * kPc;
@@ -379,7 +403,8 @@ raptor_status launch_tables(raptor_ctx* ctx, const HostTables& h, const DevTable
 {
     const bool dev = o->mem == RAPTOR_MEM_DEVICE;
     const bool fp32 = o->transfer_prec == RAPTOR_F32;
-    const int tile_w = plan.p.tile_width;
+    const Geometry geo = launch_geometry(plan.p, n_nu, fp32, o->closure >= RAPTOR_CLOSURE_MLP, o->integrator);
+    const int tile_w = geo.tile_w;
     hipStream_t s = ctx->stream;
     RAPTOR_CK(hipMemcpyAsync(d.jobs, h.jobs, nj * sizeof(DevJob), hipMemcpyHostToDevice, s), "uploading jobs");
     RAPTOR_CK(hipMemcpyAsync(d.grids, h.grids, h.n_grids * sizeof(DevGrid), hipMemcpyHostToDevice, s),
@@ -418,6 +443,8 @@ raptor_status launch_tables(raptor_ctx* ctx, const HostTables& h, const DevTable
     p.mlp_Wlo = ctx->mlp.Wlo.p;
     p.refill_threshold = plan.p.refill_threshold;
     p.tile_shift = tile_w == 8 ? 3 : tile_w == 16 ? 4 : tile_w == 32 ? 5 : 6;
+    p.rays_per_wave = geo.rays;
+    p.rays_shift = geo.rays == 16 ? 4 : geo.rays == 32 ? 5 : 6;
 
     if (o->launch == RAPTOR_LAUNCH_GRAPH) {
         raptor_status gs = launch_graph(ctx, p, n_nu, fp32, plan, nj, d.out);
@@ -482,7 +509,9 @@ raptor_status run_jobs(raptor_ctx* ctx, const JobIn* in, int nj, int n_nu, const
     std::vector<const raptor_grid*> gl(nj);
     std::vector<double> nus((size_t)nj * n_nu), pixsr(nj);
     HostTables h{jobs.data(), grids.data(), gl.data(), nus.data(), pixsr.data()};
-    raptor_status fs = fill_tables(ctx, in, nj, n_nu, o, plan.p.tile_width, &h);
+    const Geometry geo = launch_geometry(plan.p, n_nu, o->transfer_prec == RAPTOR_F32,
+                                         o->closure >= RAPTOR_CLOSURE_MLP, o->integrator);
+    raptor_status fs = fill_tables(ctx, in, nj, n_nu, o, geo.tile_w, geo.rays, &h);
     if (fs != RAPTOR_OK) return fs;
 
     // ---- device buffers of the context, grown on demand
@@ -871,7 +900,8 @@ raptor_status raptor_trace_batch_noalloc(raptor_ctx* ctx, const raptor_camera* c
     LaunchPlan plan;
     if ((s = plan_for(ctx, n_nu, fp32, &plan, opts->closure >= RAPTOR_CLOSURE_MLP, false)) != RAPTOR_OK) return s;
     HostTables h{na.jobs, na.grids, na.gl, na.nus, na.pixsr};
-    if ((s = fill_tables(ctx, na.in, n_cams, n_nu, opts, plan.p.tile_width, &h)) != RAPTOR_OK) return s;
+    const Geometry geo = launch_geometry(plan.p, n_nu, fp32, opts->closure >= RAPTOR_CLOSURE_MLP, opts->integrator);
+    if ((s = fill_tables(ctx, na.in, n_cams, n_nu, opts, geo.tile_w, geo.rays, &h)) != RAPTOR_OK) return s;
     // the launch's buffers, carved from the scratch in 256-byte aligned regions
     unsigned char* base = static_cast<unsigned char*>(ctx->noalloc_scratch);
     size_t off = 0;
@@ -969,14 +999,18 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     double bms;
     if ((s = time_plan(bp, &bms)) != RAPTOR_OK) return s;
     // coordinate descent over the plan fields
-    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256, 512}, {0, 2, 4}, {1, 8, 16, 32}, {8, 16, 64}};
+    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256, 512}, {0, 2, 4}, {1, 8, 16, 32}, {8, 16, 64},
+                                                  {64, 32, 16}};
+    const bool mlpc_c = o.closure >= RAPTOR_CLOSURE_MLP;
     for (int field = 0; field < (int)values.size(); ++field) {
         for (int v : values[field]) {
             raptor_plan c = bp;
             int* slot = field == 0 ? &c.min_waves_per_simd : field == 1 ? &c.threads : field == 2 ? &c.blocks_per_cu
-                      : field == 3 ? &c.refill_threshold : &c.tile_width;
+                      : field == 3 ? &c.refill_threshold : field == 4 ? &c.tile_width : &c.rays_per_wave;
             if (*slot == v) continue;
             *slot = v;
+            // rays per wave below 64 only where the instantiation keeps one sample per lane
+            if (field == 5 && launch_geometry(c, n_nu, fp32, mlpc_c, o.integrator).rays != v) continue;
             double ms;
             if ((s = time_plan(c, &ms)) != RAPTOR_OK) return s;
             if (ms < bms) {
@@ -1013,7 +1047,8 @@ raptor_status raptor_kernel_info(raptor_ctx* ctx, int32_t n_nu, int32_t transfer
               "reading kernel attributes");
     RAPTOR_CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                   &per_cu, trace_kernel_symbol(n_nu, fp32, plan->min_waves_per_simd, mlpc), plan->threads,
-                  trace_kernel_lds(n_nu, fp32, plan->min_waves_per_simd, plan->threads, mlpc, INTEG_RK4)),
+                  trace_kernel_lds(n_nu, fp32, plan->min_waves_per_simd, plan->threads, mlpc, INTEG_RK4,
+                                   launch_geometry(*plan, n_nu, fp32, mlpc, INTEG_RK4).rays)),
               "querying occupancy");
     if (vgprs) *vgprs = regs;
     if (scratch_bytes) *scratch_bytes = spill;

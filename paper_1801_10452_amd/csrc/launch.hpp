@@ -22,7 +22,10 @@ const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc = fals
 // dynamic LDS bytes of a trace-kernel work-group of `threads` lanes (mlpc: plus the staged network)
 // Dynamic LDS bytes of a trace launch; the same (wpe, mlpc, integ) select the instantiation in
 // trace_kernel_symbol, whose sample queue this sizes.
-size_t trace_kernel_lds(int max_nu, bool fp32, int wpe, int threads, bool mlpc, int integ);
+size_t trace_kernel_lds(int max_nu, bool fp32, int wpe, int threads, bool mlpc, int integ, int rays = 64);
+// whether the instantiation keeps one queued sample per lane with the intensity in LDS (the
+// variants that may run fewer than 64 rays per wave)
+bool trace_kernel_one_slot(int max_nu, bool fp32, int wpe, bool mlpc, int integ);
 // Waves-per-SIMD variant actually instantiated for a requested one.
 int kernel_wpe(int wpe, bool mlpc, int integ);
 

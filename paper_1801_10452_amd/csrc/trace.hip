@@ -299,12 +299,17 @@ struct Queue {
     static constexpr int WAVES_PER_CU = 4 * (WPE >= 3 ? 3 : 2);
     static constexpr int BUDGET = (163840 - (MLPC ? mlp::LDS_NET_BYTES : 0)) / WAVES_PER_CU;
     static constexpr int K = bytes_for(3) <= BUDGET ? 3 : bytes_for(2) <= BUDGET ? 2 : 1;
-    static constexpr int SLOTS = 64 * K;
-    static constexpr size_t FIELD_BYTES = (size_t)N_FIELDS * SLOTS * sizeof(double);
-    static constexpr size_t RES_BYTES = (size_t)2 * NNU * SLOTS * sizeof(double);
-    static constexpr size_t MAP_BYTES = (size_t)SLOTS * sizeof(int);
-    static constexpr size_t INFO_BYTES = 64 * sizeof(int);   // job index of each lane's ray
-    static constexpr size_t PER_WAVE = (FIELD_BYTES + RES_BYTES + MAP_BYTES + INFO_BYTES + 15) / 16 * 16;
+    // a wave's area for `rays` rays per wave (64, or fewer with a one-sample queue): fields
+    // [N_FIELDS][slots], results [slots][2 NNU], slot map [slots], job index of each lane [64]
+    static constexpr size_t field_bytes(int rays) { return (size_t)N_FIELDS * rays * K * sizeof(double); }
+    static constexpr size_t res_bytes(int rays) { return (size_t)2 * NNU * rays * K * sizeof(double); }
+    static constexpr size_t map_bytes(int rays) { return (size_t)rays * K * sizeof(int); }
+    static constexpr size_t INFO_BYTES = 64 * sizeof(int);
+    static constexpr size_t per_wave(int rays)
+    {
+        return (field_bytes(rays) + res_bytes(rays) + map_bytes(rays) + INFO_BYTES + 15) / 16 * 16;
+    }
+    static constexpr size_t PER_WAVE = per_wave(64);
 };
 
 __device__ inline void wave_lds_sync()
@@ -368,21 +373,21 @@ __device__ inline bool eval_sample(const TraceParams& p, const double* q, const 
 // Transfer<TT>'s words in the sample's queue slot, in the fields the evaluation no longer needs
 // (every field but the step length, which the fold still reads).
 constexpr int SETUP_FIELDS[9] = {0, 1, 2, 3, 4, 5, 6, 8, 9};
-template <class TT, int SLOTS>
+template <class TT, int FS, int SS>
 __device__ inline void store_setup(double* fields, int s, const Transfer<TT>& tr)
 {
     static_assert(Transfer<TT>::WORDS <= 9, "the transfer set-up fits the sample's free queue fields");
     double w[Transfer<TT>::WORDS];
     tr.to_words(w);
 #pragma unroll
-    for (int k = 0; k < Transfer<TT>::WORDS; ++k) fields[SETUP_FIELDS[k] * SLOTS + s] = w[k];
+    for (int k = 0; k < Transfer<TT>::WORDS; ++k) fields[SETUP_FIELDS[k] * FS + s * SS] = w[k];
 }
-template <class TT, int SLOTS>
+template <class TT, int FS, int SS>
 __device__ inline void load_setup(const double* fields, int s, Transfer<TT>& tr)
 {
     double w[Transfer<TT>::WORDS];
 #pragma unroll
-    for (int k = 0; k < Transfer<TT>::WORDS; ++k) w[k] = fields[SETUP_FIELDS[k] * SLOTS + s];
+    for (int k = 0; k < Transfer<TT>::WORDS; ++k) w[k] = fields[SETUP_FIELDS[k] * FS + s * SS];
     tr.from_words(w);
 }
 
@@ -513,13 +518,21 @@ trace_kernel(TraceParams p)
     // registers, and every round is evaluated frequency-parallel, each (sample, frequency) pair
     // folded into that row by the lane that computes it.
     constexpr bool FUSED = !MLPC && K == 1 && NNU > 1;
+    // rays per wave: lanes [0, RAYS) trace rays (the plan may give a one-sample-queue kernel
+    // fewer than 64, the other lanes then only work in the sample rounds); RAYS * K queue slots
+    const int RAYS = FUSED ? p.rays_per_wave : 64;
+    // field f of queue slot s is fields[f * FS + s * SS]: field-major for the multi-slot queues,
+    // slot-major (each sample's ten fields together) for the one-slot queues, whose slot count
+    // varies with the rays per wave -- the strides stay compile-time constants either way
+    constexpr int FS = FUSED ? 1 : 64 * K;
+    constexpr int SS = FUSED ? N_FIELDS : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    unsigned char* wbase = smem + (size_t)(threadIdx.x >> 6) * Q::PER_WAVE;
-    double* fields = reinterpret_cast<double*>(wbase);                                  // [N_FIELDS][SLOTS]
-    double* res = reinterpret_cast<double*>(wbase + Q::FIELD_BYTES);                    // [SLOTS][2*NNU]
-    int* slot_map = reinterpret_cast<int*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES);      // [SLOTS]
-    int* lane_job = reinterpret_cast<int*>(wbase + Q::FIELD_BYTES + Q::RES_BYTES + Q::MAP_BYTES);
+    unsigned char* wbase = smem + (size_t)(threadIdx.x >> 6) * Q::per_wave(RAYS);
+    double* fields = reinterpret_cast<double*>(wbase);                                        // see FS, SS
+    double* res = reinterpret_cast<double*>(wbase + Q::field_bytes(RAYS));                    // [slots][2*NNU]
+    int* slot_map = reinterpret_cast<int*>(wbase + Q::field_bytes(RAYS) + Q::res_bytes(RAYS));   // [slots]
+    int* lane_job = reinterpret_cast<int*>(wbase + Q::field_bytes(RAYS) + Q::res_bytes(RAYS) + Q::map_bytes(RAYS));
     const double M = p.M;
     // learned closure: the work-group's copy of the network, after the queues of its waves
     unsigned char* lds_net = smem + (size_t)(blockDim.x >> 6) * Q::PER_WAVE;
@@ -556,9 +569,10 @@ trace_kernel(TraceParams p)
 
     while (true) {
         // ------------------------------------------------------------ refill idle lanes
-        unsigned long long idle = __ballot(!active);
+        const bool ray_lane = lane < RAYS;
+        unsigned long long idle = __ballot(!active && ray_lane);
         int n_idle = __popcll(idle);
-        if (n_idle >= p.refill_threshold || n_idle == 64) {
+        if (n_idle >= p.refill_threshold || n_idle == RAYS) {
             while (n_idle > 0) {
                 if (next == end) {
                     if (drained) break;
@@ -569,21 +583,21 @@ trace_kernel(TraceParams p)
                         drained = true;
                         break;
                     }
-                    next = (long long)t * 64;
-                    end = next + 64;
+                    next = (long long)t * RAYS;
+                    end = next + RAYS;
                 }
                 const long long avail = end - next;
                 const unsigned rank = lane_rank(idle);
-                if (!active && (long long)rank < avail) {
+                if (!active && ray_lane && (long long)rank < avail) {
                     const long long ray = next + rank;
-                    const long long tile = ray >> 6;
-                    const int slot = (int)(ray & 63);
+                    const long long tile = FUSED ? ray >> p.rays_shift : ray >> 6;
+                    const int slot = (int)(ray & (RAYS - 1));
                     job = find_job(p.jobs, p.n_jobs, tile);
                     const DevJob& J = p.jobs[job];
                     const long long lt = tile - J.tile_base;
                     const int tw = 1 << p.tile_shift;
                     const int px = (int)(lt % J.tiles_x) * tw + (slot & (tw - 1));
-                    const int py = (int)(lt / J.tiles_x) * (64 >> p.tile_shift) + (slot >> p.tile_shift);
+                    const int py = (int)(lt / J.tiles_x) * (RAYS >> p.tile_shift) + (slot >> p.tile_shift);
                     if (px < J.nx && py < J.ny) {
                         const double alpha = -J.fov + (px + 0.5) * J.dalpha;
                         const double beta = -J.fov + (py + 0.5) * J.dbeta;
@@ -610,7 +624,7 @@ trace_kernel(TraceParams p)
                     }
                 }
                 next += (avail < n_idle) ? avail : n_idle;
-                idle = __ballot(!active);
+                idle = __ballot(!active && ray_lane);
                 n_idle = __popcll(idle);
             }
         }
@@ -662,16 +676,16 @@ trace_kernel(TraceParams p)
             if (status == RAY_RUNNING && pl::in_plasma(p.grids[grid], y[1])) {
                 // queue the sample point
                 const int s = lane * K + pending;
-                fields[0 * Q::SLOTS + s] = y[0];
-                fields[1 * Q::SLOTS + s] = y[1];
-                fields[2 * Q::SLOTS + s] = y[2];
-                fields[3 * Q::SLOTS + s] = y[3];
-                fields[4 * Q::SLOTS + s] = y[4];
-                fields[5 * Q::SLOTS + s] = y[5];
-                fields[6 * Q::SLOTS + s] = y[7];
-                fields[7 * Q::SLOTS + s] = -dl;
-                fields[8 * Q::SLOTS + s] = sth;
-                fields[9 * Q::SLOTS + s] = cth;
+                fields[0 * FS + s * SS] = y[0];
+                fields[1 * FS + s * SS] = y[1];
+                fields[2 * FS + s * SS] = y[2];
+                fields[3 * FS + s * SS] = y[3];
+                fields[4 * FS + s * SS] = y[4];
+                fields[5 * FS + s * SS] = y[5];
+                fields[6 * FS + s * SS] = y[7];
+                fields[7 * FS + s * SS] = -dl;
+                fields[8 * FS + s * SS] = sth;
+                fields[9 * FS + s * SS] = cth;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
                     if (k == pending) qstep[k] = steps;
@@ -716,10 +730,10 @@ trace_kernel(TraceParams p)
                     const int s = slot_map[lane];
                     double q[N_FIELDS];
 #pragma unroll
-                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * FS + s * SS];
                     Transfer<TT> tr;
                     zamo = setup_sample<TT>(p, q, lane_info(p, lane_job[s]), tr);
-                    store_setup<TT, Q::SLOTS>(fields, s, tr);
+                    store_setup<TT, FS, SS>(fields, s, tr);
                 }
                 c_zamo += __popcll(__ballot(zamo));
                 wave_lds_sync();
@@ -738,7 +752,7 @@ trace_kernel(TraceParams p)
                     const int f0 = (int)chunk * c;
                     const int f1 = (f0 + c < li.n_nu) ? f0 + c : li.n_nu;
                     Transfer<TT> tr;
-                    load_setup<TT, Q::SLOTS>(fields, s, tr);
+                    load_setup<TT, FS, SS>(fields, s, tr);
                     double* Ir = res + s * 2 * NNU;
                     double* Tr = Ir + NNU;
                     constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
@@ -788,8 +802,8 @@ trace_kernel(TraceParams p)
                 }
                 if (is < n_eval && chunk == 0) {
                     const int s = slot_map[is];
-                    fields[8 * Q::SLOTS + s] = tmin;
-                    fields[9 * Q::SLOTS + s] = dtmax;
+                    fields[8 * FS + s * SS] = tmin;
+                    fields[9 * FS + s * SS] = dtmax;
                 }
             } else if (!MLPC && NNU > 1 && n_eval < 64) {
                 // fewer samples than lanes: the (sample, frequency) pairs are spread over the
@@ -801,10 +815,10 @@ trace_kernel(TraceParams p)
                     const int s = slot_map[lane];
                     double q[N_FIELDS];
 #pragma unroll
-                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * FS + s * SS];
                     Transfer<TT> tr;
                     zamo = setup_sample<TT>(p, q, lane_info(p, lane_job[s / K]), tr);
-                    store_setup<TT, Q::SLOTS>(fields, s, tr);
+                    store_setup<TT, FS, SS>(fields, s, tr);
                 }
                 c_zamo += __popcll(__ballot(zamo));
                 wave_lds_sync();
@@ -818,7 +832,7 @@ trace_kernel(TraceParams p)
                     const int f0 = (int)((unsigned)lane - is * per) * c;
                     const int f1 = (f0 + c < li.n_nu) ? f0 + c : li.n_nu;
                     Transfer<TT> tr;
-                    load_setup<TT, Q::SLOTS>(fields, s, tr);
+                    load_setup<TT, FS, SS>(fields, s, tr);
                     constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
                     for (int f = f0; f < f1; f += G) {
                         const int cnt = f1 - f;
@@ -848,7 +862,7 @@ trace_kernel(TraceParams p)
                     const int s = has ? slot_map[i] : 0;
                     double q[N_FIELDS];
 #pragma unroll
-                    for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * Q::SLOTS + s] : 1.0;
+                    for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * FS + s * SS] : 1.0;
                     double A[NNU], dt[NNU];
                     eval_round_mlp<NNU, TT>(p, lds_net, has, q, lane_info(p, lane_job[s / K]), A, dt, c_zamo,
                                             c_fallback, c_dropped);
@@ -865,7 +879,7 @@ trace_kernel(TraceParams p)
                         const int s = slot_map[i];
                         double q[N_FIELDS];
 #pragma unroll
-                        for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * Q::SLOTS + s];
+                        for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * FS + s * SS];
                         double A[NNU], dt[NNU];
                         zamo = eval_sample<NNU, TT>(p, q, lane_info(p, lane_job[s / K]), A, dt);
 #pragma unroll
@@ -885,8 +899,8 @@ trace_kernel(TraceParams p)
             bool cut = false;
             if (FUSED && take > 0) {
                 const int s = lane;   // K = 1
-                if (p.tau_step > 0.0) rt_rate = fields[9 * Q::SLOTS + s] / fields[7 * Q::SLOTS + s];
-                if (p.tau_cutoff > 0.0 && fields[8 * Q::SLOTS + s] >= p.tau_cutoff) {
+                if (p.tau_step > 0.0) rt_rate = fields[9 * FS + s * SS] / fields[7 * FS + s * SS];
+                if (p.tau_cutoff > 0.0 && fields[8 * FS + s * SS] >= p.tau_cutoff) {
                     cut = true;
                     status = RAY_OPAQUE;
                     steps = qstep[0];
@@ -907,7 +921,7 @@ trace_kernel(TraceParams p)
                         }
                     }
                     // d tau / d|lambda| of this sample (the last one folded sets the next step)
-                    if (p.tau_step > 0.0) rt_rate = dtmax / fields[7 * Q::SLOTS + s];
+                    if (p.tau_step > 0.0) rt_rate = dtmax / fields[7 * FS + s * SS];
                     if (p.tau_cutoff > 0.0 && tmin >= p.tau_cutoff) {
                         cut = true;
                         status = RAY_OPAQUE;
@@ -923,7 +937,7 @@ trace_kernel(TraceParams p)
                     if (j < left) {
 #pragma unroll
                         for (int f = 0; f < N_FIELDS; ++f)
-                            fields[f * Q::SLOTS + lane * K + j] = fields[f * Q::SLOTS + lane * K + j + take];
+                            fields[f * FS + (lane * K + j) * SS] = fields[f * FS + (lane * K + j + take) * SS];
                     }
                 }
 #pragma unroll
@@ -1073,7 +1087,9 @@ hipError_t launch_trace(const TraceParams& p, int max_nu, bool fp32, int wpe, in
     const void* fn = trace_kernel_symbol(max_nu, fp32, wpe, p.closure >= CL_MLP, p.integrator);
     void* args[] = {const_cast<TraceParams*>(&p)};
     return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args,
-                           trace_kernel_lds(max_nu, fp32, wpe, threads, p.closure >= CL_MLP, p.integrator), st);
+                           trace_kernel_lds(max_nu, fp32, wpe, threads, p.closure >= CL_MLP, p.integrator,
+                                            p.rays_per_wave),
+                           st);
 }
 
 size_t flux_partials(int n_jobs, int max_nu) { return (size_t)n_jobs * max_nu * FLUX_SPLIT; }
@@ -1091,28 +1107,38 @@ hipError_t launch_flux(const DevJob* jobs, int n_jobs, const double* out, const 
     return hipGetLastError();
 }
 
-size_t trace_kernel_lds(int max_nu, bool fp32, int wpe, int threads, bool mlpc, int integ)
+// Visit the queue type of the instantiation that trace_kernel_symbol picks for the same arguments.
+template <class F>
+auto with_queue(int max_nu, bool fp32, int wpe, bool mlpc, int integ, F f)
 {
-    // the queue of the instantiation that trace_kernel_symbol picks for the same arguments
     const int w = kernel_wpe(wpe, mlpc, integ);
-    const int waves = threads / 64;
-    auto per_w = [&](auto tt, auto m, auto w) -> size_t {
+    auto per_w = [&](auto tt, auto m, auto w) {
         using TT = decltype(tt);
         constexpr bool M = decltype(m)::value;
         constexpr int W = decltype(w)::value;
-        if (max_nu <= 1) return Queue<1, TT, M, W>::PER_WAVE;
-        if (max_nu <= 4) return Queue<4, TT, M, W>::PER_WAVE;
-        if (max_nu <= 8) return Queue<8, TT, M, W>::PER_WAVE;
-        if (max_nu <= 16) return Queue<16, TT, M, W>::PER_WAVE;
-        return Queue<32, TT, M, W>::PER_WAVE;
+        if (max_nu <= 1) return f(Queue<1, TT, M, W>{});
+        if (max_nu <= 4) return f(Queue<4, TT, M, W>{});
+        if (max_nu <= 8) return f(Queue<8, TT, M, W>{});
+        if (max_nu <= 16) return f(Queue<16, TT, M, W>{});
+        return f(Queue<32, TT, M, W>{});
     };
-    auto per_q = [&](auto tt, auto m) -> size_t {
+    auto per_q = [&](auto tt, auto m) {
         return w == 3 ? per_w(tt, m, std::integral_constant<int, 3>{}) : per_w(tt, m, std::integral_constant<int, 2>{});
     };
-    auto per = [&](auto tt) -> size_t {
-        return mlpc ? per_q(tt, std::true_type{}) : per_q(tt, std::false_type{});
-    };
-    return waves * (fp32 ? per(0.0f) : per(0.0)) + (mlpc ? (size_t)mlp::LDS_NET_BYTES : 0);
+    auto per = [&](auto tt) { return mlpc ? per_q(tt, std::true_type{}) : per_q(tt, std::false_type{}); };
+    return fp32 ? per(0.0f) : per(0.0);
+}
+
+bool trace_kernel_one_slot(int max_nu, bool fp32, int wpe, bool mlpc, int integ)
+{
+    return !mlpc && max_nu > 1 && with_queue(max_nu, fp32, wpe, mlpc, integ, [](auto q) { return decltype(q)::K == 1; });
+}
+
+size_t trace_kernel_lds(int max_nu, bool fp32, int wpe, int threads, bool mlpc, int integ, int rays)
+{
+    const size_t per_wave =
+        with_queue(max_nu, fp32, wpe, mlpc, integ, [&](auto q) { return decltype(q)::per_wave(rays); });
+    return (size_t)(threads / 64) * per_wave + (mlpc ? (size_t)mlp::LDS_NET_BYTES : 0);
 }
 
 const void* trace_kernel_symbol(int max_nu, bool fp32, int wpe, bool mlpc, int integ)

@@ -72,7 +72,8 @@ class CStats(C.Structure):
 
 class CPlan(C.Structure):
     _fields_ = [("threads", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_threshold", C.c_int32),
-                ("tile_width", C.c_int32), ("min_waves_per_simd", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("tile_width", C.c_int32), ("min_waves_per_simd", C.c_int32), ("rays_per_wave", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -402,8 +403,10 @@ def trace_batch_noalloc(ctx, cams, grids, nu, opts, images, flux=None):
     return st
 
 
-def make_plan(threads=256, blocks_per_cu=0, refill_threshold=1, tile_width=8, min_waves_per_simd=2) -> CPlan:
-    return CPlan(threads, blocks_per_cu, refill_threshold, tile_width, min_waves_per_simd, (C.c_int32 * 3)())
+def make_plan(threads=256, blocks_per_cu=0, refill_threshold=1, tile_width=8, min_waves_per_simd=2,
+              rays_per_wave=64) -> CPlan:
+    return CPlan(threads, blocks_per_cu, refill_threshold, tile_width, min_waves_per_simd, rays_per_wave,
+                 (C.c_int32 * 2)())
 
 
 def _batch_args(cams, grids, nu):

@@ -12,7 +12,9 @@ pytestmark = pytest.mark.gpu
 
 PLANS = [dict(), dict(threads=64), dict(threads=128, tile_width=16), dict(tile_width=64, refill_threshold=32),
          dict(min_waves_per_simd=1), dict(min_waves_per_simd=2, blocks_per_cu=1),
-         dict(min_waves_per_simd=3, refill_threshold=8, tile_width=32), dict(threads=512, blocks_per_cu=4)]
+         dict(min_waves_per_simd=3, refill_threshold=8, tile_width=32), dict(threads=512, blocks_per_cu=4),
+         dict(min_waves_per_simd=3, rays_per_wave=32, tile_width=16), dict(min_waves_per_simd=3, rays_per_wave=16),
+         dict(rays_per_wave=16, tile_width=64)]
 
 
 @pytest.fixture(scope="module")
@@ -52,9 +54,40 @@ def test_every_plan_gives_the_same_images(R, ctx, prec, integ):
     ctx.release_grid(gh)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_rays_per_wave_same_images(R, ctx, prec):
+    """Twelve frequencies (one queued sample per lane in every variant): 64, 32 and 16 rays per
+    wave, with tiles as wide as the rays or narrower, give the same images bit for bit, and the
+    installed plan reports the rays and the tile width the launch uses."""
+    cam = S.Camera(spin=0.5, incl_deg=30.0, nx=80, ny=56)   # ragged in both directions for every tile
+    grid = S.make_grid(128, 128, a_gen=0.5, dtype=np.float32)
+    gh = ctx.upload_grid(grid)
+    nu = S.spectrum_freqs(12, 1e10, 1e13)
+    tp = R.F32 if prec == "f32" else R.F64
+    opts = R.default_opts(transfer_prec=tp)
+    ref = None
+    for rays, tw, w in ((64, 8, 3), (32, 16, 3), (32, 32, 2), (16, 8, 1), (16, 64, 3), (32, 8, 2)):
+        R.set_plan(ctx, len(nu), tp, R.make_plan(rays_per_wave=rays, tile_width=tw, min_waves_per_simd=w))
+        got = R.get_plan(ctx, len(nu), tp)
+        assert got.rays_per_wave == rays and got.tile_width == min(tw, rays)
+        img, flux, st = ctx.trace_spectrum(cam, gh, nu, opts)
+        if ref is None:
+            ref, ref_flux, ref_st = img.copy(), np.array(flux), st
+            assert np.abs(ref).max() > 0
+            continue
+        print(f"[rays per wave {prec}] {rays} rays, tiles {tw}, {w} waves/SIMD: max |diff| "
+              f"{np.abs(img - ref).max():.3e}, kernel_ms {st.kernel_ms:.3f}", flush=True)
+        assert np.array_equal(img, ref) and np.array_equal(np.array(flux), ref_flux), (rays, tw, w)
+        assert (st.ray_steps, st.samples, st.rays) == (ref_st.ray_steps, ref_st.samples, ref_st.rays)
+    # where the variant keeps several samples per lane (one frequency) the plan runs 64 rays
+    R.set_plan(ctx, 1, tp, R.make_plan(rays_per_wave=16))
+    assert R.get_plan(ctx, 1, tp).rays_per_wave == 64
+    ctx.release_grid(gh)
+
+
 def test_invalid_plans_are_refused(R, ctx):
     for bad in (dict(threads=96), dict(tile_width=12), dict(min_waves_per_simd=4), dict(refill_threshold=0),
-                dict(blocks_per_cu=-1)):
+                dict(blocks_per_cu=-1), dict(rays_per_wave=8), dict(rays_per_wave=48)):
         with pytest.raises(R.RaptorError) as e:
             R.set_plan(ctx, 1, R.F32, R.make_plan(**bad))
         assert e.value.status == R.E_INVALID
