@@ -999,18 +999,22 @@ raptor_status raptor_autotune_batch(raptor_ctx* ctx, const raptor_camera* cams, 
     double bms;
     if ((s = time_plan(bp, &bms)) != RAPTOR_OK) return s;
     // coordinate descent over the plan fields
-    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256, 512}, {0, 2, 4}, {1, 8, 16, 32}, {8, 16, 64},
-                                                  {64, 32, 16}};
+    // (rays per wave before the tile width, which it bounds)
+    const std::vector<std::vector<int>> values = {{1, 2, 3}, {64, 256, 512}, {0, 2, 4}, {1, 8, 16, 32}, {64, 32, 16},
+                                                  {8, 16, 64}};
     const bool mlpc_c = o.closure >= RAPTOR_CLOSURE_MLP;
     for (int field = 0; field < (int)values.size(); ++field) {
         for (int v : values[field]) {
             raptor_plan c = bp;
             int* slot = field == 0 ? &c.min_waves_per_simd : field == 1 ? &c.threads : field == 2 ? &c.blocks_per_cu
-                      : field == 3 ? &c.refill_threshold : field == 4 ? &c.tile_width : &c.rays_per_wave;
+                      : field == 3 ? &c.refill_threshold : field == 4 ? &c.rays_per_wave : &c.tile_width;
             if (*slot == v) continue;
             *slot = v;
-            // rays per wave below 64 only where the instantiation keeps one sample per lane
-            if (field == 5 && launch_geometry(c, n_nu, fp32, mlpc_c, o.integrator).rays != v) continue;
+            // rays per wave below 64 only where the instantiation keeps one sample per lane, and
+            // no tile wider than the rays (it would run as the narrower one already timed)
+            const Geometry cg = launch_geometry(c, n_nu, fp32, mlpc_c, o.integrator);
+            if (field == 4 && cg.rays != v) continue;
+            if (field == 5 && cg.tile_w != v) continue;
             double ms;
             if ((s = time_plan(c, &ms)) != RAPTOR_OK) return s;
             if (ms < bms) {

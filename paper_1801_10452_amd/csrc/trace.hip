@@ -305,9 +305,16 @@ struct Queue {
     static constexpr size_t res_bytes(int rays) { return (size_t)2 * NNU * rays * K * sizeof(double); }
     static constexpr size_t map_bytes(int rays) { return (size_t)rays * K * sizeof(int); }
     static constexpr size_t INFO_BYTES = 64 * sizeof(int);
+    // Several frequencies with one queued sample per lane (the kernel's FUSED form): the job
+    // indices [64] and the slot map [64] first, then one record per ray of REC doubles -- its ten
+    // queue fields, then its intensity and optical depth per frequency -- so that every address
+    // is a compile-time offset from the record of a slot whatever the rays per wave.
+    static constexpr bool ONE_SLOT = !MLPC && K == 1 && NNU > 1;
+    static constexpr int REC = N_FIELDS + 2 * NNU;
     static constexpr size_t per_wave(int rays)
     {
-        return (field_bytes(rays) + res_bytes(rays) + map_bytes(rays) + INFO_BYTES + 15) / 16 * 16;
+        return ONE_SLOT ? (size_t)512 + (size_t)rays * REC * sizeof(double)
+                        : (field_bytes(rays) + res_bytes(rays) + map_bytes(rays) + INFO_BYTES + 15) / 16 * 16;
     }
     static constexpr size_t PER_WAVE = per_wave(64);
 };
@@ -517,7 +524,7 @@ trace_kernel(TraceParams p)
     // frequency live in its row of the result area (I then tau, 2 NNU doubles) instead of
     // registers, and every round is evaluated frequency-parallel, each (sample, frequency) pair
     // folded into that row by the lane that computes it.
-    constexpr bool FUSED = !MLPC && K == 1 && NNU > 1;
+    constexpr bool FUSED = Q::ONE_SLOT;
     // rays per wave: lanes [0, RAYS) trace rays (the plan may give a one-sample-queue kernel
     // fewer than 64, the other lanes then only work in the sample rounds); RAYS * K queue slots
     const int RAYS = FUSED ? p.rays_per_wave : 64;
@@ -525,14 +532,26 @@ trace_kernel(TraceParams p)
     // slot-major (each sample's ten fields together) for the one-slot queues, whose slot count
     // varies with the rays per wave -- the strides stay compile-time constants either way
     constexpr int FS = FUSED ? 1 : 64 * K;
-    constexpr int SS = FUSED ? N_FIELDS : 1;
+    constexpr int SS = FUSED ? Q::REC : 1;
+    constexpr int RS = FUSED ? Q::REC : 2 * NNU;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     unsigned char* wbase = smem + (size_t)(threadIdx.x >> 6) * Q::per_wave(RAYS);
-    double* fields = reinterpret_cast<double*>(wbase);                                        // see FS, SS
-    double* res = reinterpret_cast<double*>(wbase + Q::field_bytes(RAYS));                    // [slots][2*NNU]
-    int* slot_map = reinterpret_cast<int*>(wbase + Q::field_bytes(RAYS) + Q::res_bytes(RAYS));   // [slots]
-    int* lane_job = reinterpret_cast<int*>(wbase + Q::field_bytes(RAYS) + Q::res_bytes(RAYS) + Q::map_bytes(RAYS));
+    double* fields;    // see FS, SS
+    double* res;       // row of slot s at res + s * RS: [NNU] intensities or contributions, then [NNU] depths
+    int* slot_map;     // [slots]
+    int* lane_job;     // [64]
+    if constexpr (FUSED) {
+        lane_job = reinterpret_cast<int*>(wbase);
+        slot_map = reinterpret_cast<int*>(wbase + 256);
+        fields = reinterpret_cast<double*>(wbase + 512);
+        res = fields + N_FIELDS;
+    } else {
+        fields = reinterpret_cast<double*>(wbase);
+        res = reinterpret_cast<double*>(wbase + Q::field_bytes(64));
+        slot_map = reinterpret_cast<int*>(wbase + Q::field_bytes(64) + Q::res_bytes(64));
+        lane_job = reinterpret_cast<int*>(wbase + Q::field_bytes(64) + Q::res_bytes(64) + Q::map_bytes(64));
+    }
     const double M = p.M;
     // learned closure: the work-group's copy of the network, after the queues of its waves
     unsigned char* lds_net = smem + (size_t)(blockDim.x >> 6) * Q::PER_WAVE;
@@ -618,7 +637,7 @@ trace_kernel(TraceParams p)
                         for (int f = 0; f < NNU; ++f) { I[f] = 0.0; tau[f] = 0.0; }
                         if (FUSED) {
 #pragma unroll
-                            for (int f = 0; f < 2 * NNU; ++f) res[lane * 2 * NNU + f] = 0.0;
+                            for (int f = 0; f < 2 * NNU; ++f) res[lane * RS + f] = 0.0;
                         }
                         active = true;
                     }
@@ -753,7 +772,7 @@ trace_kernel(TraceParams p)
                     const int f1 = (f0 + c < li.n_nu) ? f0 + c : li.n_nu;
                     Transfer<TT> tr;
                     load_setup<TT, FS, SS>(fields, s, tr);
-                    double* Ir = res + s * 2 * NNU;
+                    double* Ir = res + s * RS;
                     double* Tr = Ir + NNU;
                     constexpr int G = NNU < FREQ_GROUP ? NNU : FREQ_GROUP;
                     int f = f0;
@@ -847,8 +866,8 @@ trace_kernel(TraceParams p)
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
                             if (g < cnt) {
-                                res[s * 2 * NNU + f + g] = A[g];
-                                res[s * 2 * NNU + NNU + f + g] = dt[g];
+                                res[s * RS + f + g] = A[g];
+                                res[s * RS + NNU + f + g] = dt[g];
                             }
                         }
                     }
@@ -869,8 +888,8 @@ trace_kernel(TraceParams p)
                     if (has) {
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
-                            res[s * 2 * NNU + f] = A[f];
-                            res[s * 2 * NNU + NNU + f] = dt[f];
+                            res[s * RS + f] = A[f];
+                            res[s * RS + NNU + f] = dt[f];
                         }
                     }
                 } else {
@@ -884,8 +903,8 @@ trace_kernel(TraceParams p)
                         zamo = eval_sample<NNU, TT>(p, q, lane_info(p, lane_job[s / K]), A, dt);
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
-                            res[s * 2 * NNU + f] = A[f];
-                            res[s * 2 * NNU + NNU + f] = dt[f];
+                            res[s * RS + f] = A[f];
+                            res[s * RS + NNU + f] = dt[f];
                         }
                     }
                     c_zamo += __popcll(__ballot(zamo));
@@ -914,10 +933,10 @@ trace_kernel(TraceParams p)
 #pragma unroll
                     for (int f = 0; f < NNU; ++f) {
                         if (f < n_nu) {
-                            I[f] = I[f] + (double)attenuation<TT>(tau[f]) * res[s * 2 * NNU + f];
-                            tau[f] = tau[f] + res[s * 2 * NNU + NNU + f];
+                            I[f] = I[f] + (double)attenuation<TT>(tau[f]) * res[s * RS + f];
+                            tau[f] = tau[f] + res[s * RS + NNU + f];
                             tmin = ::fmin(tmin, tau[f]);
-                            dtmax = ::fmax(dtmax, res[s * 2 * NNU + NNU + f]);
+                            dtmax = ::fmax(dtmax, res[s * RS + NNU + f]);
                         }
                     }
                     // d tau / d|lambda| of this sample (the last one folded sets the next step)
@@ -960,7 +979,7 @@ trace_kernel(TraceParams p)
             double* o = p.out + J.out_base + pix;
 #pragma unroll
             for (int f = 0; f < NNU; ++f)
-                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : (FUSED ? res[lane * 2 * NNU + f] : I[f]);
+                if (f < n_nu) o[f * npix] = (status == RAY_NUMERIC) ? 0.0 : (FUSED ? res[lane * RS + f] : I[f]);
             if (p.ray_status) p.ray_status[J.pix_base + pix] = status;
             if (p.ray_steps) p.ray_steps[J.pix_base + pix] = steps;
             active = false;
