@@ -139,7 +139,7 @@ def spectrum_section(args, R, S, ctx, prec):
     for name, slow, cl in forms:
         progress(f"spectrum {name}: autotuning, then timing")
         tune = R.default_opts(transfer_prec=prec, slow_light=slow, closure=cl)
-        plan, _ = R.autotune_batch(ctx, [cam], [gh], nu, tune, reps=1)
+        plan, _ = R.autotune_batch(ctx, [cam], [gh], nu, tune, reps=3)   # ~10 ms per trial: best of three
         opts = R.default_opts(transfer_prec=prec, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, slow_light=slow,
                               closure=cl)
         r = time_spectrum(ctx, R, cam, gh, nu, opts, images, flux, args.steps, args.warmup)
