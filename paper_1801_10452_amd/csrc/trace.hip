@@ -265,7 +265,8 @@ __device__ inline float attenuation<float>(double tau) { return rt::exp_mixed(-t
 
 // ---------------------------------------------------------------------------------------
 // Sample compaction.  A lane whose ray takes a step inside the plasma does not evaluate the
-// sample at once: it queues the point (ten doubles) in its wave's LDS area, up to K per lane.
+// sample at once: it queues the point (ten doubles) in its wave's LDS area, up to K per lane,
+// its k-th in slot k * 64 + lane (consecutive lanes in consecutive slots of a queue layer).
 // The wave evaluates queued samples together -- sample i of the selected list on lane i mod 64
 // -- so the expensive part (MKS map, gather, fluid frame, closure) runs on full waves: once 64
 // samples are queued (or a lane's queue is full) it evaluates the largest multiple of 64 of
@@ -694,7 +695,7 @@ trace_kernel(TraceParams p)
             }
             if (status == RAY_RUNNING && pl::in_plasma(p.grids[grid], y[1])) {
                 // queue the sample point
-                const int s = lane * K + pending;
+                const int s = pending * 64 + lane;   // queue layer `pending` of this lane
                 fields[0 * FS + s * SS] = y[0];
                 fields[1 * FS + s * SS] = y[1];
                 fields[2 * FS + s * SS] = y[2];
@@ -734,7 +735,7 @@ trace_kernel(TraceParams p)
                 const unsigned long long b = __ballot(pending > k);
                 const unsigned rank = lane_rank(b);
                 if (pending > k && listed + rank < n_eval) {
-                    slot_map[listed + rank] = lane * K + k;
+                    slot_map[listed + rank] = k * 64 + lane;
                     take = k + 1;
                 }
                 const unsigned c = __popcll(b);
@@ -836,7 +837,7 @@ trace_kernel(TraceParams p)
 #pragma unroll
                     for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * FS + s * SS];
                     Transfer<TT> tr;
-                    zamo = setup_sample<TT>(p, q, lane_info(p, lane_job[s / K]), tr);
+                    zamo = setup_sample<TT>(p, q, lane_info(p, lane_job[s & 63]), tr);
                     store_setup<TT, FS, SS>(fields, s, tr);
                 }
                 c_zamo += __popcll(__ballot(zamo));
@@ -846,7 +847,7 @@ trace_kernel(TraceParams p)
                 const unsigned is = ((unsigned)lane * mul) >> 16;
                 if (is < n_eval) {
                     const int s = slot_map[is];
-                    const LaneInfo li = lane_info(p, lane_job[s / K]);
+                    const LaneInfo li = lane_info(p, lane_job[s & 63]);
                     const int c = (int)(((unsigned)(li.n_nu + per - 1) * mul) >> 16);
                     const int f0 = (int)((unsigned)lane - is * per) * c;
                     const int f1 = (f0 + c < li.n_nu) ? f0 + c : li.n_nu;
@@ -883,7 +884,7 @@ trace_kernel(TraceParams p)
 #pragma unroll
                     for (int f = 0; f < N_FIELDS; ++f) q[f] = has ? fields[f * FS + s * SS] : 1.0;
                     double A[NNU], dt[NNU];
-                    eval_round_mlp<NNU, TT>(p, lds_net, has, q, lane_info(p, lane_job[s / K]), A, dt, c_zamo,
+                    eval_round_mlp<NNU, TT>(p, lds_net, has, q, lane_info(p, lane_job[s & 63]), A, dt, c_zamo,
                                             c_fallback, c_dropped);
                     if (has) {
 #pragma unroll
@@ -900,7 +901,7 @@ trace_kernel(TraceParams p)
 #pragma unroll
                         for (int f = 0; f < N_FIELDS; ++f) q[f] = fields[f * FS + s * SS];
                         double A[NNU], dt[NNU];
-                        zamo = eval_sample<NNU, TT>(p, q, lane_info(p, lane_job[s / K]), A, dt);
+                        zamo = eval_sample<NNU, TT>(p, q, lane_info(p, lane_job[s & 63]), A, dt);
 #pragma unroll
                         for (int f = 0; f < NNU; ++f) {
                             res[s * RS + f] = A[f];
@@ -928,7 +929,7 @@ trace_kernel(TraceParams p)
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (!FUSED && k < take && !cut) {
-                    const int s = lane * K + k;
+                    const int s = k * 64 + lane;
                     double tmin = 1e300, dtmax = 0.0;
 #pragma unroll
                     for (int f = 0; f < NNU; ++f) {
@@ -956,7 +957,7 @@ trace_kernel(TraceParams p)
                     if (j < left) {
 #pragma unroll
                         for (int f = 0; f < N_FIELDS; ++f)
-                            fields[f * FS + (lane * K + j) * SS] = fields[f * FS + (lane * K + j + take) * SS];
+                            fields[f * FS + (j * 64 + lane) * SS] = fields[f * FS + ((j + take) * 64 + lane) * SS];
                     }
                 }
 #pragma unroll
