@@ -55,16 +55,23 @@ def test_every_plan_gives_the_same_images(R, ctx, prec, integ):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_rays_per_wave_same_images(R, ctx, prec):
+@pytest.mark.parametrize("depth", ["plain", "cutoff", "tau_step"])
+def test_rays_per_wave_same_images(R, ctx, prec, depth):
     """Twelve frequencies (one queued sample per lane in every variant): 64, 32 and 16 rays per
-    wave, with tiles as wide as the rays or narrower, give the same images bit for bit, and the
-    installed plan reports the rays and the tile width the launch uses."""
-    cam = S.Camera(spin=0.5, incl_deg=30.0, nx=80, ny=56)   # ragged in both directions for every tile
-    grid = S.make_grid(128, 128, a_gen=0.5, dtype=np.float32)
+    wave, with tiles as wide as the rays or narrower, give the same images bit for bit -- also
+    with the optical-depth cut-off and the optical-depth-aware step, whose per-sample reductions
+    run across the lanes that share a sample -- and the installed plan reports the rays and the
+    tile width the launch uses."""
+    import math
+    cam = S.Camera(spin=0.9375, incl_deg=60.0, nx=80, ny=56)   # ragged in both directions for every tile
+    grid = S.make_grid(128, 128, a_gen=0.9375, dtype=np.float32)
     gh = ctx.upload_grid(grid)
-    nu = S.spectrum_freqs(12, 1e10, 1e13)
+    # the cut-off needs a ray opaque at every frequency: low frequencies where the torus is thick
+    nu = S.spectrum_freqs(12, 1e9, 1e13) if depth == "plain" else S.spectrum_freqs(12, 1e8, 2e9)
     tp = R.F32 if prec == "f32" else R.F64
-    opts = R.default_opts(transfer_prec=tp)
+    kw = {"plain": {}, "cutoff": dict(tau_cutoff=math.log(1000.0)),
+          "tau_step": dict(tau_cutoff=math.log(1000.0), tau_step=0.1)}[depth]
+    opts = R.default_opts(transfer_prec=tp, **kw)
     ref = None
     for rays, tw, w in ((64, 8, 3), (32, 16, 3), (32, 32, 2), (16, 8, 1), (16, 64, 3), (32, 8, 2)):
         R.set_plan(ctx, len(nu), tp, R.make_plan(rays_per_wave=rays, tile_width=tw, min_waves_per_simd=w))
@@ -75,10 +82,15 @@ def test_rays_per_wave_same_images(R, ctx, prec):
             ref, ref_flux, ref_st = img.copy(), np.array(flux), st
             assert np.abs(ref).max() > 0
             continue
-        print(f"[rays per wave {prec}] {rays} rays, tiles {tw}, {w} waves/SIMD: max |diff| "
+        print(f"[rays per wave {prec} {depth}] {rays} rays, tiles {tw}, {w} waves/SIMD: max |diff| "
               f"{np.abs(img - ref).max():.3e}, kernel_ms {st.kernel_ms:.3f}", flush=True)
         assert np.array_equal(img, ref) and np.array_equal(np.array(flux), ref_flux), (rays, tw, w)
-        assert (st.ray_steps, st.samples, st.rays) == (ref_st.ray_steps, ref_st.samples, ref_st.rays)
+        assert (st.ray_steps, st.samples, st.rays, st.n_opaque) == (ref_st.ray_steps, ref_st.samples, ref_st.rays,
+                                                                    ref_st.n_opaque)
+    print(f"[rays per wave {prec} {depth}] opaque {ref_st.n_opaque}, step limit {ref_st.n_maxstep} of {ref_st.rays} rays",
+          flush=True)
+    if depth == "cutoff":
+        assert ref_st.n_opaque > 0   # the cut-off ends some rays here
     # where the variant keeps several samples per lane (one frequency) the plan runs 64 rays
     R.set_plan(ctx, 1, tp, R.make_plan(rays_per_wave=16))
     assert R.get_plan(ctx, 1, tp).rays_per_wave == 64
