@@ -179,7 +179,8 @@ def test_fp32_transfer_error(R, ctx, orc):
 def test_production_batch_sampled_parity(R, ctx, orc, prec):
     """The benchmark's launch: 9 images of 512 x 512 (spins {0, 0.5, 0.9375} x inclinations
     {30, 60, 85}) on float32 256^2 grids in one batch, 230 GHz; per image 24 seeded random pixels
-    and the 24 brightest pixels of the GPU image against the oracle."""
+    and the 24 brightest pixels of the GPU image against the oracle; with FP32 transfer also the
+    benchmark's own launch (device memory, graph capture and replay) bit for bit against that."""
     sets = S.production_set()
     cams = [c for c, _ in sets]
     handles = {}
@@ -207,6 +208,21 @@ def test_production_batch_sampled_parity(R, ctx, orc, prec):
         worst = max(worst, e.max())
     print(f"[production {prec}] worst sampled rel err {worst:.3e}", flush=True)
     assert worst <= TOL_FP64
+    if prec == "f32":
+        # the benchmark's launch configuration (device-resident outputs, the launch captured as a
+        # graph and replayed) gives bitwise the images and fluxes checked above
+        import torch
+        dimg = torch.empty(imgs.size, dtype=torch.float64, device="cuda")
+        dflux = torch.empty(flux.size, dtype=torch.float64, device="cuda")
+        gopts = R.default_opts(transfer_prec=R.F32, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH)
+        for rep in range(2):
+            dimg.fill_(-1.0)
+            dflux.fill_(-1.0)
+            torch.cuda.synchronize()
+            gst = ctx.trace_batch(cams, grids, [S.NU_230], gopts, images=dimg, flux=dflux)[2]
+            assert np.array_equal(dimg.cpu().numpy(), np.ravel(imgs)), rep
+            assert np.array_equal(dflux.cpu().numpy(), np.ravel(flux)), rep
+            assert gst.ray_steps == st.ray_steps and gst.samples == st.samples
     for h in handles.values():
         ctx.release_grid(h)
 
