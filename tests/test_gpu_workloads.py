@@ -72,6 +72,35 @@ def test_spectrum_slow_light_full_size(R, ctx, orc, slow_set, prec, slow):
     ctx.release_grid(gh)
 
 
+@pytest.mark.parametrize("slow", [0, 1])
+def test_spectrum_autotuned_graph_replay(R, ctx, slow_set, slow):
+    """The 24-frequency spectrum in its timed form (FP32 transfer, fast and slow light): the plan the
+    autotuner picks, with the launch captured as a graph and replayed, gives bitwise the images
+    and fluxes of the default plan's direct launch, the one checked against the oracle above."""
+    import torch
+    cam, grid, nu = slow_set
+    gh = ctx.upload_grid(grid)
+    opts = R.default_opts(transfer_prec=R.F32, slow_light=slow)
+    ref_i, ref_f, ref_st = ctx.trace_spectrum(cam, gh, nu, opts)
+    default_plan = R.get_plan(ctx, len(nu), R.F32)
+    plan, ms = R.autotune_batch(ctx, [cam], [gh], nu, opts, reps=1)
+    print(f"[spectrum slow={slow} autotune] plan {plan.as_dict()} best kernel {ms:.2f} ms (default {ref_st.kernel_ms:.2f} ms)",
+          flush=True)
+    img = torch.empty(ref_i.size, dtype=torch.float64, device="cuda")
+    flux = torch.empty(ref_f.size, dtype=torch.float64, device="cuda")
+    graph = R.default_opts(transfer_prec=R.F32, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH, slow_light=slow)
+    for rep in range(2):
+        img.fill_(-1.0)
+        flux.fill_(-1.0)
+        torch.cuda.synchronize()
+        st = ctx.trace_spectrum(cam, gh, nu, graph, images=img, flux=flux)[2]
+        assert np.array_equal(img.cpu().numpy(), np.ravel(ref_i)), rep
+        assert np.array_equal(flux.cpu().numpy(), np.ravel(ref_f)), rep
+        assert st.ray_steps == ref_st.ray_steps and st.samples == ref_st.samples
+    R.set_plan(ctx, len(nu), R.F32, default_plan)
+    ctx.release_grid(gh)
+
+
 def test_uneven_batch_full_size(R, ctx, orc):
     cams = S.batch_jobs()
     grid = S.make_grid(256, 256, a_gen=0.9375, dtype=np.float32)
