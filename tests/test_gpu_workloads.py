@@ -132,17 +132,21 @@ def test_uneven_batch_full_size(R, ctx, orc):
 def test_uneven_batch_autotuned_graph_replay(R, ctx):
     """The uneven batch in its timed form: the autotuner picks a plan on the 256 images (exact
     closure, FP32 transfer), and the graph-captured launch replayed twice under that plan gives
-    bitwise the images and fluxes of the direct launch under the same plan."""
+    bitwise the images and fluxes of the direct launch under the same plan, which equal those of
+    the default plan (checked against the oracle above) bit for bit."""
     import torch
     cams = S.batch_jobs()
     grid = S.make_grid(256, 256, a_gen=0.9375, dtype=np.float32)
     gh = ctx.upload_grid(grid)
     grids = [gh] * len(cams)
     nu = S.NU_VLBI
+    dflt_i, dflt_f, _ = ctx.trace_batch(cams, grids, nu, R.default_opts(transfer_prec=R.F32))
+    default_plan = R.get_plan(ctx, len(nu), R.F32)
     plan, ms = R.autotune_batch(ctx, cams, grids, nu, R.default_opts(transfer_prec=R.F32), reps=1)
     print(f"[uneven batch autotune] plan {plan.as_dict()} best kernel {ms:.1f} ms", flush=True)
     n = sum(c.nx * c.ny for c in cams) * len(nu)
     ref_i, ref_f, ref_st = ctx.trace_batch(cams, grids, nu, R.default_opts(transfer_prec=R.F32))
+    assert np.array_equal(ref_i, dflt_i) and np.array_equal(ref_f, dflt_f)
     img = torch.empty(n, dtype=torch.float64, device="cuda")
     flux = torch.empty((len(cams), len(nu)), dtype=torch.float64, device="cuda")
     graph = R.default_opts(transfer_prec=R.F32, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH)
@@ -153,6 +157,7 @@ def test_uneven_batch_autotuned_graph_replay(R, ctx):
         assert st.ray_steps == ref_st.ray_steps
     print(f"[uneven batch graph] {st.kernel_ms:.1f} ms, {st.ray_steps / st.kernel_ms * 1e3:.3e} ray-steps/s",
           flush=True)
+    R.set_plan(ctx, len(nu), R.F32, default_plan)
     ctx.release_grid(gh)
 
 
