@@ -214,10 +214,10 @@ def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
     for name, cl in (("exact", R.CLOSURE_EXACT), ("k2_paper", R.CLOSURE_K2_PAPER), ("mlp_split", R.CLOSURE_MLP),
                      ("mlp_bf16", R.CLOSURE_MLP_BF16)):
         opts = R.default_opts(transfer_prec=R.F32, closure=cl)
-        _, flux, st = ctx.trace_batch(cams, grids, [S.NU_230], opts)
-        res[name] = (np.asarray(flux).ravel(), st)
+        img, flux, st = ctx.trace_batch(cams, grids, [S.NU_230], opts)
+        res[name] = (np.asarray(flux).ravel(), st, img)
     fx = res["exact"][0]
-    for name, (f, st) in res.items():
+    for name, (f, st, _) in res.items():
         rel = f / fx - 1
         print(f"[mlp gain] {name:9s} kernel_ms {st.kernel_ms:8.2f} ray-steps/s {st.ray_steps / st.kernel_ms * 1e3:.3e} "
               f"max|dF/F| {np.abs(rel).max():.3e} fallback {st.n_mlp_fallback}/{st.samples}", flush=True)
@@ -231,6 +231,20 @@ def test_trained_network_flux_gate_and_what_it_gains(R, ctx):
     assert e_mlp.max() <= 1e-3
     assert e_mlp.max() < e_k2.min()
     assert fb < 0.1
+    # the learned form in the benchmark's launch (device-resident outputs, the launch captured as
+    # a graph and replayed) gives the direct launch's images and fluxes bit for bit
+    import torch
+    img_m = res["mlp_split"][2]
+    dimg = torch.empty(img_m.size, dtype=torch.float64, device="cuda")
+    dflux = torch.empty(len(cams), dtype=torch.float64, device="cuda")
+    gopts = R.default_opts(transfer_prec=R.F32, closure=R.CLOSURE_MLP, mem=R.MEM_DEVICE, launch=R.LAUNCH_GRAPH)
+    for k in range(2):
+        dimg.fill_(-1.0)
+        dflux.fill_(-1.0)
+        torch.cuda.synchronize()
+        ctx.trace_batch(cams, grids, [S.NU_230], gopts, images=dimg, flux=dflux)
+        assert np.array_equal(dimg.cpu().numpy(), np.ravel(img_m)), k
+        assert np.array_equal(dflux.cpu().numpy(), res["mlp_split"][0]), k
     for h in handles.values():
         ctx.release_grid(h)
 
