@@ -209,8 +209,9 @@ def batch_jobs(n_images=256, seed=S0 + 200, res_choices=(64, 128, 256, 512)):
     return cams
 
 
-def mlp_samples(n, seed=S0 + 100, nu_ratio=(1e-2, 1e6), thetae=(0.1, 100.0), cos_max=0.999):
-    """Closure inputs (ln(nu/nu_c), ln Theta_e, cos theta_B), log-uniform / uniform."""
+def mlp_samples(n, seed=S0 + 100, nu_ratio=(1e-2, 1e8), thetae=(0.1, 100.0), cos_max=0.999):
+    """Closure inputs (ln(nu/nu_c), ln Theta_e, cos theta_B), log-uniform / uniform over the
+    learned closure's box."""
     u = uniform(seed, np.arange(3 * n, dtype=np.uint64)).reshape(n, 3)
     l1 = np.log(nu_ratio[0]) + u[:, 0] * (np.log(nu_ratio[1]) - np.log(nu_ratio[0]))
     l2 = np.log(thetae[0]) + u[:, 1] * (np.log(thetae[1]) - np.log(thetae[0]))
